@@ -1,0 +1,231 @@
+/*
+ * lbm_sparse.h - C ABI of the sparse-lattice D3Q19 lattice Boltzmann library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Wittmann, Zeiser, Hager, Wellein, "Modeling and analyzing
+ * performance for highly optimized propagation steps of the lattice Boltzmann
+ * method on sparse lattices" (arXiv:1410.0412).
+ *
+ * Only fluid nodes are stored (Sect. 1). Their order is fixed by an
+ * enumeration function: lexicographic sorting with a blocking factor, or a
+ * space-filling curve (Sect. 1, Sect. 5.6, Sect. 6). Neighbours are reached
+ * through an adjacency list of 18 four-byte indices per node (Sect. 4, Loop
+ * Balance). One time step is a fused collide-and-propagate update of
+ * eq. (1) (Sect. 2) in one of two propagation patterns (Sect. 4): the
+ * two-grid one-step pull algorithm (OS-NT) or the one-grid AA pattern, each
+ * with plain indirect addressing or with reduced indirect addressing (RIA,
+ * Sect. 4.1), which run-length codes nodes whose access pattern is that of
+ * the previous node shifted by one.
+ *
+ * Conventions
+ * - Every function returns 0 (LBM_OK) on success or a negative LBM_E* code;
+ *   lbm_last_error() then returns a message (per thread, valid until the next
+ *   failing call on that thread). No C++ exception crosses this interface.
+ * - Voxel boxes are nx*ny*nz, C order: voxel id = (x*ny + y)*nz + z.
+ * - D3Q19 directions q = 0..18: 0 rest; 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z;
+ *   7 (+1,+1,0), 8 (-1,-1,0), 9 (+1,-1,0), 10 (-1,+1,0), 11 (+1,0,+1),
+ *   12 (-1,0,-1), 13 (+1,0,-1), 14 (-1,0,+1), 15 (0,+1,+1), 16 (0,-1,-1),
+ *   17 (0,+1,-1), 18 (0,-1,+1). Opposite of odd q is q+1, of even q>0 is q-1.
+ * - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *   memory of the current device. The library never allocates device
+ *   memory: callers pass every device buffer and keep it alive until the
+ *   work queued on it has finished.
+ * - Device work is queued asynchronously on the HIP stream given to the
+ *   solver; errors of queued kernels surface as LBM_EDEVICE at a later call
+ *   that synchronises (moments, export) or checks the launch status.
+ * - Handles are not thread-safe; use one handle per thread.
+ */
+#ifndef LBM_SPARSE_H
+#define LBM_SPARSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,  /* invalid argument (null pointer, bad size or flag)   */
+  LBM_ERANGE = -2,  /* a size does not fit the index type                  */
+  LBM_ENOMEM = -3,  /* host allocation failed                              */
+  LBM_EDEVICE = -4, /* HIP runtime error                                   */
+  LBM_ESTATE = -5   /* call not valid in the object's current state        */
+};
+
+enum { LBM_ORDER_LEX = 0, LBM_ORDER_MORTON = 1 };
+enum { LBM_PATTERN_AA = 0, LBM_PATTERN_OSNT = 1 };
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* ====================================================================== */
+/* Host lattice: enumeration, adjacency list, RIA runs, wave tables        */
+/* ====================================================================== */
+
+typedef struct lbm_lattice lbm_lattice;
+
+/*
+ * Build the sparse lattice of a voxel mask (host, synchronous).
+ *
+ * solid          host, nx*ny*nz bytes, C order; nonzero marks a solid voxel.
+ * periodic_mask  bit 0/1/2: x/y/z axis periodic. On a non-periodic axis the
+ *                outside of the box counts as solid (halfway bounce-back).
+ * order          LBM_ORDER_LEX: lexicographic sorting (Sect. 5.6), x slowest
+ *                and z fastest, visiting block x block x block tiles in that
+ *                order and voxels inside a tile in that order; block = 0 (or
+ *                >= the largest extent, or 1) means no blocking.
+ *                LBM_ORDER_MORTON: Morton space-filling curve (bits of x, y, z
+ *                interleaved, x most significant per triple); block ignored.
+ *
+ * Node n is the n-th fluid voxel in that order. For q = 1..18 the adjacency
+ * entry of node n is the node at the upstream site x_n - c_q (pull scheme,
+ * Sect. 4), or -1 if that site is solid or outside the box. Runs (Sect. 4.1):
+ * node n > 0 continues the run of node n-1 iff for every q its entry equals
+ * the entry of n-1 plus one, or both are -1; runs are maximal.
+ *
+ * Errors: LBM_EINVAL for null pointers or non-positive extents or a negative
+ * block; LBM_ERANGE if nx*ny*nz or the fluid-node count exceeds 2^31-1 or an
+ * extent exceeds 2^21 (Morton); LBM_ENOMEM. On success *out owns all tables
+ * until lbm_lattice_free.
+ */
+int lbm_lattice_build(const uint8_t* solid, int32_t nx, int32_t ny, int32_t nz,
+                      uint32_t periodic_mask, int32_t order, int32_t block,
+                      lbm_lattice** out);
+
+/* Table sizes: N fluid nodes, R runs, W = ceil(N/64) wavefront tiles. */
+int lbm_lattice_sizes(const lbm_lattice* lat, int64_t* n_fluid, int64_t* n_runs,
+                      int64_t* n_waves);
+
+/* node_voxel: host int32[N]; voxel id of node n. */
+int lbm_lattice_copy_nodes(const lbm_lattice* lat, int32_t* node_voxel);
+
+/* adj: host int32[18*ld], ld >= N; entry of direction q (1..18) for node n at
+ * adj[(q-1)*ld + n]. Columns N..ld-1 are filled with -1. */
+int lbm_lattice_copy_adjacency(const lbm_lattice* lat, int32_t* adj, int64_t ld);
+
+/* run_start: host int32[R+1]; first node of each run, then N (the block
+ * vector of Sect. 4.1 stored as prefix sums of the run lengths). */
+int lbm_lattice_copy_runs(const lbm_lattice* lat, int32_t* run_start);
+
+/*
+ * Per-wavefront RIA encoding (64-node tiles; one GPU lane per node):
+ * run_delta  host int32[18*ldr], ldr >= R: for run r with head h,
+ *            run_delta[(q-1)*ldr + r] = adj_q(h) - h, or INT32_MIN if
+ *            adj_q(h) = -1. Inside run r, adj_q(n) = n + run_delta.
+ *            Columns R..ldr-1 are filled with INT32_MIN.
+ * head_bits  host uint64[W]; bit l of word w set iff node 64w+l heads a run.
+ * run_base   host int32[W]; (number of run heads below node 64w) - 1.
+ * Node 64w+l lies in run run_base[w] + popcount(head_bits[w] & bits 0..l).
+ */
+int lbm_lattice_copy_wave_tables(const lbm_lattice* lat, int32_t* run_delta, int64_t ldr,
+                                 uint64_t* head_bits, int32_t* run_base);
+
+void lbm_lattice_free(lbm_lattice* lat);
+
+/* ====================================================================== */
+/* Device solver                                                           */
+/* ====================================================================== */
+
+typedef struct lbm_params {
+  double tau;        /* BGK relaxation time, > 1/2                           */
+  double force[3];   /* constant body-force density F                       */
+  double rho0;       /* reference density of deviation storage (F32/F16)    */
+  int32_t pattern;   /* LBM_PATTERN_AA or LBM_PATTERN_OSNT                   */
+  int32_t ria;       /* 0: adjacency list; 1: RIA wave tables                */
+  int32_t precision; /* LBM_F64 (FP64 storage and arithmetic), LBM_F32 or
+                        LBM_F16 (storage of f_q - w_q*rho0, FP32 arithmetic) */
+  int32_t flags;     /* reserved, must be 0                                  */
+  int64_t n_fluid;   /* N                                                    */
+  int64_t n_runs;    /* R (RIA only)                                         */
+  int64_t ldf;       /* elements between direction streams, >= N, multiple
+                        of 64                                                */
+  int64_t lda;       /* adjacency row stride (>= N), adjacency only          */
+  int64_t ldr;       /* run_delta row stride (>= R), RIA only                */
+} lbm_params;
+
+typedef struct lbm_buffers {
+  void* pdf[2];               /* device PDF grids, 19*ldf elements of the
+                                 storage type each; pdf[1] only for OS-NT    */
+  const int32_t* adj;         /* device [18][lda] (ria = 0)                  */
+  const int32_t* run_delta;   /* device [18][ldr] (ria = 1)                  */
+  const uint64_t* head_bits;  /* device [W]       (ria = 1)                  */
+  const int32_t* run_base;    /* device [W]       (ria = 1)                  */
+} lbm_buffers;
+
+typedef struct lbm_solver lbm_solver;
+
+/* Workspace bytes the solver needs (device scratch for reductions). */
+int lbm_solver_workspace_bytes(const lbm_params* p, int64_t* bytes);
+
+/*
+ * Create a solver over caller-owned device buffers (borrowed, not copied).
+ * workspace: device, at least lbm_solver_workspace_bytes. hip_stream: the
+ * hipStream_t all work is queued on (NULL: the default stream). The solver
+ * starts at t = 0 with undefined PDFs; call an init or import first.
+ * Errors: LBM_EINVAL (tau <= 1/2, bad flags, missing buffers, ldf < N or not
+ * a multiple of 64, lda < N, ldr < R), LBM_ERANGE (N >= 2^31 or a slot index
+ * 19*ldf that does not fit 2^31 - 1 elements), LBM_ENOMEM.
+ */
+int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace,
+                      int64_t workspace_bytes, void* hip_stream, lbm_solver** out);
+
+/* Set the stream later work is queued on. */
+int lbm_solver_set_stream(lbm_solver* s, void* hip_stream);
+
+/*
+ * f(0) = feq(rho, u) on every node and t = 0 (one kernel).
+ * rho: device double[N] or NULL (rho0 everywhere); u: device double[3*N]
+ * (component-major: u[a*N + n]) or NULL (zero velocity).
+ */
+int lbm_solver_init_equilibrium(lbm_solver* s, const double* rho, const double* u);
+
+/*
+ * Advance n_steps time steps (one kernel launch per step, asynchronous).
+ * AA: even t runs the direct step, odd t the indirect step (Sect. 4);
+ * OS-NT: pull step into the other grid, then the grids swap.
+ */
+int lbm_solver_step(lbm_solver* s, int64_t n_steps);
+
+/* Current time step t. */
+int lbm_solver_time(const lbm_solver* s, int64_t* t);
+
+/*
+ * Macroscopic fields of the pre-collision PDFs f(t): rho[n] and
+ * u[a*N + n] = j_a / rho (device double, either may be NULL), and totals
+ * (device double[4]: mass, jx, jy, jz summed over all nodes in a fixed
+ * order; may be NULL). Synchronises the stream.
+ */
+int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals);
+
+/* f(t) in natural order: device double[19*N], f[q*N + n]. Synchronises. */
+int lbm_solver_export_pdfs(lbm_solver* s, double* f);
+
+/* Set the state to f (device double[19*N], natural order) at time t >= 0. */
+int lbm_solver_import_pdfs(lbm_solver* s, const double* f, int64_t t);
+
+void lbm_solver_free(lbm_solver* s);
+
+/* ====================================================================== */
+/* Bandwidth micro-benchmarks (Sect. 5.2, Table 3, GPU analogues)          */
+/* ====================================================================== */
+
+/*
+ * kind 0 "copy": dst[i] = src[i] for n doubles (STREAM copy).
+ * kind 1 "CNT-19A": 19 streams of n doubles, stride ld, copied src -> dst
+ *        (the traffic pattern of the OS-NT step).
+ * kind 2 "U-19A": 19 streams of n doubles, stride ld, updated in place in dst
+ *        (the traffic pattern of the AA even step); src unused.
+ * kind 3 "U-1A": one stream of n doubles updated in place in dst; src unused.
+ * kind 4 "CNT-1A": copy of one stream of n doubles (same as kind 0).
+ * Asynchronous on hip_stream.
+ */
+int lbm_bench_stream(int32_t kind, const double* src, double* dst, int64_t n, int64_t ld,
+                     void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_SPARSE_H */

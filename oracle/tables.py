@@ -146,7 +146,7 @@ def wave_tables(adj, run_start, wave=WAVE):
     for l in range(wave):
         bits |= hb[:, l].astype(np.uint64) << np.uint64(l)
     per_wave = hb.sum(axis=1)
-    base = (np.concatenate([[0], np.cumsum(per_wave)[:-1]]) - 1).astype(np.int32)
+    base = (np.cumsum(per_wave) - per_wave - 1).astype(np.int32)
     return delta, bits, base
 
 

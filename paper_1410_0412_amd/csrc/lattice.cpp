@@ -1,0 +1,297 @@
+// Host-side sparse-lattice builder: enumeration, adjacency list, RIA runs and
+// their per-wavefront encoding (declared in include/lbm_sparse.h).
+//
+// Sect. 1 and Sect. 4: only fluid nodes are stored, in the order fixed by an
+// enumeration function, and every node keeps 18 four-byte neighbour indices
+// (the rest direction is addressed directly). Sect. 4.1: a node whose access
+// pattern equals the previous node's shifted by one needs no index load; such
+// runs are stored run-length coded. Sect. 5.6: lexicographic sorting with a
+// blocking factor B, or a space-filling curve, as enumeration.
+//
+// All tables are built in O(voxels) passes that run in parallel over node or
+// voxel ranges; only the Morton order needs a sort (LSD radix on the keys).
+
+#include "common.hpp"
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+using namespace lbm;
+
+struct lbm_lattice {
+  int32_t nx = 0, ny = 0, nz = 0;
+  int64_t N = 0, R = 0, W = 0;
+  std::vector<int32_t> node_voxel;  // [N]
+  std::vector<int32_t> adj;         // [18][N]
+  std::vector<int32_t> run_start;   // [R+1]
+  std::vector<int32_t> run_delta;   // [18][R]
+  std::vector<uint64_t> head_bits;  // [W]
+  std::vector<int32_t> run_base;    // [W]
+};
+
+namespace {
+
+// Pull direction vectors c_q, q = 0..18 (same order as the kernels use).
+constexpr int kC[19][3] = {
+    {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+    {-1, 0, 1}, {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+template <class F>
+void parallel_for(int64_t n, F&& body) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 1, 32));
+  if (n < (int64_t)1 << 16) nt = 1;
+  if (nt == 1) {
+    body(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (int64_t t = 0; t < nt; ++t) {
+    int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back([&body, lo, hi] { body(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+inline uint64_t spread3(uint64_t v) {
+  // place bit b of v at bit 3b (v < 2^21)
+  v &= 0x1fffffULL;
+  v = (v | (v << 32)) & 0x1f00000000ffffULL;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+  v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+  v = (v | (v << 2)) & 0x1249249249249249ULL;
+  return v;
+}
+
+// LSD radix sort of (key, voxel) pairs by the low key_bits bits of the key.
+void radix_sort(std::vector<uint64_t>& key, std::vector<int32_t>& val, int key_bits) {
+  std::vector<uint64_t> k2(key.size());
+  std::vector<int32_t> v2(val.size());
+  const int digit = 11;
+  const uint64_t dmask = (1u << digit) - 1;
+  for (int shift = 0; shift < key_bits; shift += digit) {
+    std::vector<int64_t> count((1 << digit) + 1, 0);
+    for (uint64_t k : key) count[((k >> shift) & dmask) + 1]++;
+    for (int i = 0; i < (1 << digit); ++i) count[i + 1] += count[i];
+    for (size_t i = 0; i < key.size(); ++i) {
+      int64_t dst = count[(key[i] >> shift) & dmask]++;
+      k2[dst] = key[i];
+      v2[dst] = val[i];
+    }
+    key.swap(k2);
+    val.swap(v2);
+  }
+}
+
+int enumerate(lbm_lattice* L, const uint8_t* solid, int32_t order, int32_t block) {
+  const int64_t nx = L->nx, ny = L->ny, nz = L->nz;
+  auto& out = L->node_voxel;
+  const int64_t maxext = std::max(nx, std::max(ny, nz));
+  if (order == LBM_ORDER_LEX) {
+    const int64_t B = block;
+    if (B <= 1 || B >= maxext) {
+      for (int64_t v = 0; v < nx * ny * nz; ++v)
+        if (!solid[v]) out.push_back((int32_t)v);
+    } else {
+      for (int64_t bx = 0; bx < nx; bx += B)
+        for (int64_t by = 0; by < ny; by += B)
+          for (int64_t bz = 0; bz < nz; bz += B)
+            for (int64_t x = bx; x < std::min(nx, bx + B); ++x)
+              for (int64_t y = by; y < std::min(ny, by + B); ++y)
+                for (int64_t z = bz; z < std::min(nz, bz + B); ++z) {
+                  int64_t v = (x * ny + y) * nz + z;
+                  if (!solid[v]) out.push_back((int32_t)v);
+                }
+    }
+    return LBM_OK;
+  }
+  if (order == LBM_ORDER_MORTON) {
+    if (maxext > (1 << 21)) return fail(LBM_ERANGE, "Morton order needs extents <= 2^21");
+    int bits = 0;
+    while ((int64_t(1) << bits) < maxext) ++bits;
+    std::vector<uint64_t> keys;
+    for (int64_t v = 0; v < nx * ny * nz; ++v) {
+      if (solid[v]) continue;
+      uint64_t x = v / (ny * nz), y = (v / nz) % ny, z = v % nz;
+      keys.push_back((spread3(x) << 2) | (spread3(y) << 1) | spread3(z));
+      out.push_back((int32_t)v);
+    }
+    radix_sort(keys, out, std::max(1, 3 * bits));
+    return LBM_OK;
+  }
+  return fail(LBM_EINVAL, "unknown order %d", order);
+}
+
+void build_adjacency(lbm_lattice* L, uint32_t periodic) {
+  const int64_t nx = L->nx, ny = L->ny, nz = L->nz, N = L->N;
+  const int64_t ext[3] = {nx, ny, nz};
+  std::vector<int32_t> node_of((size_t)(nx * ny * nz), -1);
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t n = lo; n < hi; ++n) node_of[L->node_voxel[n]] = (int32_t)n;
+  });
+  L->adj.assign((size_t)(18 * N), -1);
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t n = lo; n < hi; ++n) {
+      const int64_t v = L->node_voxel[n];
+      const int64_t x[3] = {v / (ny * nz), (v / nz) % ny, v % nz};
+      for (int q = 1; q < 19; ++q) {
+        int64_t u[3];
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) {
+          u[a] = x[a] - kC[q][a];
+          if (u[a] < 0 || u[a] >= ext[a]) {
+            if (periodic & (1u << a))
+              u[a] = (u[a] + ext[a]) % ext[a];
+            else
+              inside = false;
+          }
+        }
+        int32_t nb = -1;
+        if (inside) nb = node_of[(u[0] * ny + u[1]) * nz + u[2]];
+        L->adj[(size_t)(q - 1) * N + n] = nb;
+      }
+    }
+  });
+}
+
+void build_runs(lbm_lattice* L) {
+  const int64_t N = L->N;
+  std::vector<uint8_t> head((size_t)N, 1);
+  const int32_t* A = L->adj.data();
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t n = std::max<int64_t>(lo, 1); n < hi; ++n) {
+      bool cont = true;
+      for (int q = 0; q < 18 && cont; ++q) {
+        const int32_t p = A[(size_t)q * N + n - 1], c = A[(size_t)q * N + n];
+        cont = (p >= 0) ? (c == p + 1) : (c < 0);
+      }
+      head[n] = cont ? 0 : 1;
+    }
+  });
+  L->run_start.clear();
+  for (int64_t n = 0; n < N; ++n)
+    if (head[n]) L->run_start.push_back((int32_t)n);
+  L->R = (int64_t)L->run_start.size();
+  L->run_start.push_back((int32_t)N);
+
+  const int64_t R = L->R;
+  L->run_delta.assign((size_t)(18 * R), INT32_MIN);
+  parallel_for(R, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      const int64_t h = L->run_start[r];
+      for (int q = 0; q < 18; ++q) {
+        const int32_t a = A[(size_t)q * N + h];
+        L->run_delta[(size_t)q * R + r] = a >= 0 ? (int32_t)(a - h) : INT32_MIN;
+      }
+    }
+  });
+
+  const int64_t W = (N + kWave - 1) / kWave;
+  L->W = W;
+  L->head_bits.assign((size_t)W, 0);
+  L->run_base.assign((size_t)W, 0);
+  for (int64_t n = 0; n < N; ++n)
+    if (head[n]) L->head_bits[n / kWave] |= (uint64_t)1 << (n % kWave);
+  int64_t heads_below = 0;
+  for (int64_t w = 0; w < W; ++w) {
+    L->run_base[w] = (int32_t)(heads_below - 1);
+    heads_below += __builtin_popcountll(L->head_bits[w]);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_lattice_build(const uint8_t* solid, int32_t nx, int32_t ny, int32_t nz,
+                      uint32_t periodic_mask, int32_t order, int32_t block, lbm_lattice** out) {
+  clear_error();
+  if (!solid || !out) return fail(LBM_EINVAL, "null pointer");
+  *out = nullptr;
+  if (nx <= 0 || ny <= 0 || nz <= 0) return fail(LBM_EINVAL, "extents must be positive");
+  if (block < 0) return fail(LBM_EINVAL, "block must be >= 0");
+  if (periodic_mask > 7u) return fail(LBM_EINVAL, "periodic_mask has bits above 2");
+  if ((int64_t)nx * ny * nz > INT32_MAX) return fail(LBM_ERANGE, "voxel count exceeds 2^31-1");
+  lbm_lattice* L = new (std::nothrow) lbm_lattice;
+  if (!L) return fail(LBM_ENOMEM, "out of host memory");
+  L->nx = nx;
+  L->ny = ny;
+  L->nz = nz;
+  try {
+    int rc = enumerate(L, solid, order, block);
+    if (rc != LBM_OK) {
+      delete L;
+      return rc;
+    }
+    L->N = (int64_t)L->node_voxel.size();
+    build_adjacency(L, periodic_mask);
+    build_runs(L);
+  } catch (const std::bad_alloc&) {
+    delete L;
+    return fail(LBM_ENOMEM, "out of host memory building the lattice");
+  }
+  *out = L;
+  return LBM_OK;
+}
+
+int lbm_lattice_sizes(const lbm_lattice* L, int64_t* n_fluid, int64_t* n_runs, int64_t* n_waves) {
+  clear_error();
+  if (!L) return fail(LBM_EINVAL, "null lattice");
+  if (n_fluid) *n_fluid = L->N;
+  if (n_runs) *n_runs = L->R;
+  if (n_waves) *n_waves = L->W;
+  return LBM_OK;
+}
+
+int lbm_lattice_copy_nodes(const lbm_lattice* L, int32_t* node_voxel) {
+  clear_error();
+  if (!L || !node_voxel) return fail(LBM_EINVAL, "null pointer");
+  if (L->N) std::memcpy(node_voxel, L->node_voxel.data(), sizeof(int32_t) * L->N);
+  return LBM_OK;
+}
+
+int lbm_lattice_copy_adjacency(const lbm_lattice* L, int32_t* adj, int64_t ld) {
+  clear_error();
+  if (!L || !adj) return fail(LBM_EINVAL, "null pointer");
+  if (ld < L->N) return fail(LBM_EINVAL, "ld < N");
+  for (int q = 0; q < 18; ++q) {
+    if (L->N) std::memcpy(adj + q * ld, L->adj.data() + q * L->N, sizeof(int32_t) * L->N);
+    std::fill(adj + q * ld + L->N, adj + (q + 1) * ld, -1);
+  }
+  return LBM_OK;
+}
+
+int lbm_lattice_copy_runs(const lbm_lattice* L, int32_t* run_start) {
+  clear_error();
+  if (!L || !run_start) return fail(LBM_EINVAL, "null pointer");
+  std::memcpy(run_start, L->run_start.data(), sizeof(int32_t) * (L->R + 1));
+  return LBM_OK;
+}
+
+int lbm_lattice_copy_wave_tables(const lbm_lattice* L, int32_t* run_delta, int64_t ldr,
+                                 uint64_t* head_bits, int32_t* run_base) {
+  clear_error();
+  if (!L) return fail(LBM_EINVAL, "null lattice");
+  if (run_delta) {
+    if (ldr < L->R) return fail(LBM_EINVAL, "ldr < R");
+    for (int q = 0; q < 18; ++q) {
+      if (L->R) std::memcpy(run_delta + q * ldr, L->run_delta.data() + q * L->R, sizeof(int32_t) * L->R);
+      std::fill(run_delta + q * ldr + L->R, run_delta + (q + 1) * ldr, INT32_MIN);
+    }
+  }
+  if (head_bits && L->W) std::memcpy(head_bits, L->head_bits.data(), sizeof(uint64_t) * L->W);
+  if (run_base && L->W) std::memcpy(run_base, L->run_base.data(), sizeof(int32_t) * L->W);
+  return LBM_OK;
+}
+
+void lbm_lattice_free(lbm_lattice* L) { delete L; }
+
+}  // extern "C"

@@ -1,0 +1,476 @@
+// Device solver and bandwidth micro-benchmarks behind the C ABI of
+// include/lbm_sparse.h: initialisation, time stepping (AA or OS-NT, with
+// adjacency list or RIA wave tables), macroscopic moments with deterministic
+// FP64 reductions, and PDF export / import in natural order.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+struct lbm_solver {
+  lbm_params p;
+  lbm_buffers b;
+  double* ws = nullptr;
+  int64_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  int64_t t = 0;
+  int cur = 0;     // OS-NT: grid that holds f*(t-1)
+  int remap = 1;   // XCD-aware tile order
+  Collision c;
+};
+
+namespace {
+
+constexpr int kRedBlocks = 1024;  // fixed grid of the reduction: deterministic sums
+
+// Which slots hold f(t) for node n: natural (AA at even t), L (AA at odd t)
+// or the pull map P (OS-NT).
+enum Layout : int { kNatural = 0, kAAOdd = 1, kPull = 2 };
+
+template <class Idx>
+__device__ __forceinline__ void state_slots(int layout, int32_t n, const Idx& idx, int64_t ldf,
+                                            int64_t (&s)[Q]) {
+  if (layout == kNatural) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] = (int64_t)q * ldf + n;
+    return;
+  }
+  int32_t a[18];
+  idx.get(n, a);
+  if (layout == kAAOdd) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] = aa_slot(q, n, a, ldf);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] = pull_slot(q, n, a, ldf);
+  }
+}
+
+template <class Idx>
+__global__ void __launch_bounds__(kBlock)
+init_eq_f64(double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, int layout,
+            const double* __restrict__ rho, const double* __restrict__ u, double rho0) {
+  const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (n64 >= N) return;
+  const int32_t n = (int32_t)n64;
+  const double r = rho ? rho[n] : rho0;
+  const double ux = u ? u[n] : 0.0, uy = u ? u[(int64_t)N + n] : 0.0, uz = u ? u[2 * (int64_t)N + n] : 0.0;
+  double feq[Q];
+  equilibrium_f64(r, ux, uy, uz, feq);
+  int64_t s[Q];
+  state_slots(layout, n, idx, ldf, s);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) F[s[q]] = feq[q];
+}
+
+template <class Idx>
+__global__ void __launch_bounds__(kBlock)
+gather_f64(const double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, int layout,
+           double* __restrict__ out) {
+  const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (n64 >= N) return;
+  const int32_t n = (int32_t)n64;
+  int64_t s[Q];
+  state_slots(layout, n, idx, ldf, s);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) out[(int64_t)q * N + n] = F[s[q]];
+}
+
+template <class Idx>
+__global__ void __launch_bounds__(kBlock)
+scatter_f64(double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, int layout,
+            const double* __restrict__ in) {
+  const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (n64 >= N) return;
+  const int32_t n = (int32_t)n64;
+  int64_t s[Q];
+  state_slots(layout, n, idx, ldf, s);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) F[s[q]] = in[(int64_t)q * N + n];
+}
+
+// rho, u = j / rho of f(t), plus per-block partial sums of rho and j.
+template <class Idx>
+__global__ void __launch_bounds__(kBlock)
+moments_f64(const double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, int layout,
+            double* __restrict__ rho_out, double* __restrict__ u_out, double* __restrict__ partial) {
+  __shared__ double red[4][kBlock];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x; n64 < N;
+       n64 += (int64_t)gridDim.x * kBlock) {
+    const int32_t n = (int32_t)n64;
+    int64_t s[Q];
+    state_slots(layout, n, idx, ldf, s);
+    double f[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = F[s[q]];
+    const double rho = density(f);
+    const double jx = momentum<0>(f), jy = momentum<1>(f), jz = momentum<2>(f);
+    if (rho_out) rho_out[n] = rho;
+    if (u_out) {
+      u_out[n] = jx / rho;
+      u_out[(int64_t)N + n] = jy / rho;
+      u_out[2 * (int64_t)N + n] = jz / rho;
+    }
+    acc[0] = acc[0] + rho;
+    acc[1] = acc[1] + jx;
+    acc[2] = acc[2] + jy;
+    acc[3] = acc[3] + jz;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = red[k][threadIdx.x] + red[k][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+finish_totals(const double* __restrict__ partial, int nparts, double* __restrict__ totals) {
+  __shared__ double red[4][kBlock];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = acc[k] + partial[i * 4 + k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = red[k][threadIdx.x] + red[k][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) totals[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------- micro-benchmarks ----
+
+typedef double vec2d __attribute__((ext_vector_type(2)));
+
+__global__ void __launch_bounds__(kBlock)
+bench_copy(const vec2d* __restrict__ src, vec2d* __restrict__ dst, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n2) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+__global__ void __launch_bounds__(kBlock)
+bench_copy_tail(const double* __restrict__ src, double* __restrict__ dst, int64_t lo, int64_t n) {
+  const int64_t i = lo + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(kBlock)
+bench_cnt19(const double* __restrict__ src, double* __restrict__ dst, int64_t n, int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = __builtin_nontemporal_load(src + q * ld + i);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q], dst + q * ld + i);
+}
+
+__global__ void __launch_bounds__(kBlock)
+bench_u19(double* __restrict__ F, int64_t n, int64_t ld, double s) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = __builtin_nontemporal_load(F + q * ld + i);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q] * s, F + q * ld + i);
+}
+
+__global__ void __launch_bounds__(kBlock)
+bench_u1(double* __restrict__ F, int64_t n, double s) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(F + i) * s, F + i);
+}
+
+// ---------------------------------------------------------------- host ----
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+int device_status(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+IndexIA index_ia(const lbm_solver* s) { return IndexIA{s->b.adj, s->p.lda}; }
+IndexRIA index_ria(const lbm_solver* s) {
+  return IndexRIA{s->b.run_delta, s->b.head_bits, s->b.run_base, s->p.ldr};
+}
+
+// Layout of f(t) in the current grid.
+int current_layout(const lbm_solver* s) {
+  if (s->p.pattern == LBM_PATTERN_OSNT) return kPull;
+  return (s->t % 2 == 0) ? kNatural : kAAOdd;
+}
+
+double* current_grid(const lbm_solver* s) {
+  return (double*)s->b.pdf[s->p.pattern == LBM_PATTERN_OSNT ? s->cur : 0];
+}
+
+template <class Fn>
+int with_index(const lbm_solver* s, Fn&& fn) {
+  if (s->p.ria)
+    fn(index_ria(s));
+  else
+    fn(index_ia(s));
+  return LBM_OK;
+}
+
+int launch_step(lbm_solver* s) {
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N == 0) {  // nothing to update; time still advances
+    if (s->p.pattern == LBM_PATTERN_OSNT) s->cur = 1 - s->cur;
+    s->t += 1;
+    return LBM_OK;
+  }
+  unsigned grid = grid_for(N);
+  if (s->remap) grid = (grid + 7) / 8 * 8;
+  const dim3 g(grid), b(kBlock);
+  const int64_t ldf = s->p.ldf;
+  if (s->p.pattern == LBM_PATTERN_AA) {
+    double* F = (double*)s->b.pdf[0];
+    if (s->t % 2 == 0) {
+      hipLaunchKernelGGL(aa_even_f64, g, b, 0, s->stream, F, N, ldf, s->c, s->remap);
+    } else {
+      with_index(s, [&](auto idx) {
+        hipLaunchKernelGGL(aa_odd_f64<decltype(idx)>, g, b, 0, s->stream, F, N, ldf, idx, s->c,
+                           s->remap);
+      });
+    }
+  } else {
+    const double* G = (const double*)s->b.pdf[s->cur];
+    double* H = (double*)s->b.pdf[1 - s->cur];
+    with_index(s, [&](auto idx) {
+      hipLaunchKernelGGL(osnt_f64<decltype(idx)>, g, b, 0, s->stream, G, H, N, ldf, idx, s->c,
+                         s->remap);
+    });
+    s->cur = 1 - s->cur;
+  }
+  s->t += 1;
+  return LBM_OK;
+}
+
+int validate(const lbm_params* p, const lbm_buffers* b) {
+  if (!p || !b) return fail(LBM_EINVAL, "null params or buffers");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 1/2");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->force[a])) return fail(LBM_EINVAL, "force must be finite");
+  if (p->pattern != LBM_PATTERN_AA && p->pattern != LBM_PATTERN_OSNT)
+    return fail(LBM_EINVAL, "unknown pattern %d", p->pattern);
+  if (p->ria != 0 && p->ria != 1) return fail(LBM_EINVAL, "ria must be 0 or 1");
+  if (p->precision != LBM_F64) return fail(LBM_EINVAL, "precision %d is not available", p->precision);
+  if (p->flags & ~1) return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->n_fluid < 0) return fail(LBM_EINVAL, "n_fluid < 0");
+  if (p->n_fluid > INT32_MAX - 64) return fail(LBM_ERANGE, "n_fluid exceeds the int32 node index");
+  if (p->ldf < p->n_fluid || p->ldf % 64 != 0) return fail(LBM_EINVAL, "ldf must be >= N and a multiple of 64");
+  if (!b->pdf[0]) return fail(LBM_EINVAL, "pdf[0] is null");
+  if (p->pattern == LBM_PATTERN_OSNT && !b->pdf[1]) return fail(LBM_EINVAL, "OS-NT needs pdf[1]");
+  if (p->ria) {
+    if (p->n_runs < 0 || (p->n_fluid > 0 && p->n_runs < 1)) return fail(LBM_EINVAL, "n_runs invalid");
+    if (p->ldr < p->n_runs) return fail(LBM_EINVAL, "ldr < n_runs");
+    if (p->n_fluid > 0 && (!b->run_delta || !b->head_bits || !b->run_base))
+      return fail(LBM_EINVAL, "RIA needs run_delta, head_bits and run_base");
+  } else {
+    if (p->lda < p->n_fluid) return fail(LBM_EINVAL, "lda < n_fluid");
+    if (p->n_fluid > 0 && !b->adj) return fail(LBM_EINVAL, "adjacency list is null");
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return error_buffer(); }
+
+int lbm_solver_workspace_bytes(const lbm_params* p, int64_t* bytes) {
+  clear_error();
+  if (!p || !bytes) return fail(LBM_EINVAL, "null pointer");
+  *bytes = (int64_t)kRedBlocks * 4 * sizeof(double);
+  return LBM_OK;
+}
+
+int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace,
+                      int64_t workspace_bytes, void* hip_stream, lbm_solver** out) {
+  clear_error();
+  if (!out) return fail(LBM_EINVAL, "null out");
+  *out = nullptr;
+  int rc = validate(p, b);
+  if (rc) return rc;
+  int64_t need = 0;
+  lbm_solver_workspace_bytes(p, &need);
+  if (!workspace || workspace_bytes < need)
+    return fail(LBM_EINVAL, "workspace must hold %lld bytes", (long long)need);
+  lbm_solver* s = new (std::nothrow) lbm_solver;
+  if (!s) return fail(LBM_ENOMEM, "out of host memory");
+  s->p = *p;
+  s->b = *b;
+  s->ws = (double*)workspace;
+  s->ws_bytes = workspace_bytes;
+  s->stream = (hipStream_t)hip_stream;
+  s->remap = (p->flags & 1) ? 0 : 1;
+  s->c.omega = 1.0 / p->tau;
+  for (int q = 0; q < Q; ++q)
+    s->c.S[q] = (3.0 * kW[q]) * cdot<double>(q, p->force[0], p->force[1], p->force[2]);
+  s->c.omega_f = (float)s->c.omega;
+  for (int q = 0; q < Q; ++q) s->c.S_f[q] = (float)s->c.S[q];
+  s->c.rho0_f = (float)p->rho0;
+  s->c.pad_ = 0.f;
+  *out = s;
+  return LBM_OK;
+}
+
+int lbm_solver_set_stream(lbm_solver* s, void* hip_stream) {
+  clear_error();
+  if (!s) return fail(LBM_EINVAL, "null solver");
+  s->stream = (hipStream_t)hip_stream;
+  return LBM_OK;
+}
+
+int lbm_solver_init_equilibrium(lbm_solver* s, const double* rho, const double* u) {
+  clear_error();
+  if (!s) return fail(LBM_EINVAL, "null solver");
+  s->t = 0;
+  s->cur = 0;
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N == 0) return LBM_OK;
+  const int layout = s->p.pattern == LBM_PATTERN_OSNT ? kPull : kNatural;
+  double* F = (double*)s->b.pdf[0];
+  with_index(s, [&](auto idx) {
+    hipLaunchKernelGGL(init_eq_f64<decltype(idx)>, dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F,
+                       N, s->p.ldf, idx, layout, rho, u, s->p.rho0);
+  });
+  return device_status("init_equilibrium");
+}
+
+int lbm_solver_step(lbm_solver* s, int64_t n_steps) {
+  clear_error();
+  if (!s) return fail(LBM_EINVAL, "null solver");
+  if (n_steps < 0) return fail(LBM_EINVAL, "n_steps < 0");
+  for (int64_t i = 0; i < n_steps; ++i) launch_step(s);
+  return device_status("step");
+}
+
+int lbm_solver_time(const lbm_solver* s, int64_t* t) {
+  clear_error();
+  if (!s || !t) return fail(LBM_EINVAL, "null pointer");
+  *t = s->t;
+  return LBM_OK;
+}
+
+int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals) {
+  clear_error();
+  if (!s) return fail(LBM_EINVAL, "null solver");
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N == 0) {
+    if (totals)  // no partials: the finishing kernel writes zeros
+      hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, s->ws, 0, totals);
+  } else {
+    const unsigned grid = std::min<unsigned>(grid_for(N), kRedBlocks);
+    const double* F = current_grid(s);
+    const int layout = current_layout(s);
+    with_index(s, [&](auto idx) {
+      hipLaunchKernelGGL(moments_f64<decltype(idx)>, dim3(grid), dim3(kBlock), 0, s->stream, F, N,
+                         s->p.ldf, idx, layout, rho, u, s->ws);
+    });
+    if (totals)
+      hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, s->ws, (int)grid, totals);
+  }
+  int rc = device_status("moments");
+  if (rc) return rc;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return device_status("moments (sync)");
+  return LBM_OK;
+}
+
+int lbm_solver_export_pdfs(lbm_solver* s, double* f) {
+  clear_error();
+  if (!s || !f) return fail(LBM_EINVAL, "null pointer");
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N > 0) {
+    const double* F = current_grid(s);
+    const int layout = current_layout(s);
+    with_index(s, [&](auto idx) {
+      hipLaunchKernelGGL(gather_f64<decltype(idx)>, dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F,
+                         N, s->p.ldf, idx, layout, f);
+    });
+  }
+  int rc = device_status("export_pdfs");
+  if (rc) return rc;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return device_status("export_pdfs (sync)");
+  return LBM_OK;
+}
+
+int lbm_solver_import_pdfs(lbm_solver* s, const double* f, int64_t t) {
+  clear_error();
+  if (!s || !f) return fail(LBM_EINVAL, "null pointer");
+  if (t < 0) return fail(LBM_EINVAL, "t < 0");
+  s->t = t;
+  s->cur = 0;
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N == 0) return LBM_OK;
+  double* F = current_grid(s);
+  const int layout = current_layout(s);
+  with_index(s, [&](auto idx) {
+    hipLaunchKernelGGL(scatter_f64<decltype(idx)>, dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F,
+                       N, s->p.ldf, idx, layout, f);
+  });
+  return device_status("import_pdfs");
+}
+
+void lbm_solver_free(lbm_solver* s) { delete s; }
+
+int lbm_bench_stream(int32_t kind, const double* src, double* dst, int64_t n, int64_t ld,
+                     void* hip_stream) {
+  clear_error();
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (n < 0) return fail(LBM_EINVAL, "n < 0");
+  if (n == 0) return LBM_OK;
+  switch (kind) {
+    case 0:
+    case 4: {
+      if (!src || !dst) return fail(LBM_EINVAL, "copy needs src and dst");
+      if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return fail(LBM_EINVAL, "copy needs 16-byte alignment");
+      const int64_t n2 = n / 2;
+      if (n2) hipLaunchKernelGGL(bench_copy, dim3(grid_for(n2)), dim3(kBlock), 0, st, (const vec2d*)src,
+                                 (vec2d*)dst, n2);
+      if (n % 2) hipLaunchKernelGGL(bench_copy_tail, dim3(1), dim3(kBlock), 0, st, src, dst, 2 * n2, n);
+      break;
+    }
+    case 1:
+      if (!src || !dst || ld < n) return fail(LBM_EINVAL, "CNT-19A needs src, dst and ld >= n");
+      hipLaunchKernelGGL(bench_cnt19, dim3(grid_for(n)), dim3(kBlock), 0, st, src, dst, n, ld);
+      break;
+    case 2:
+      if (!dst || ld < n) return fail(LBM_EINVAL, "U-19A needs dst and ld >= n");
+      hipLaunchKernelGGL(bench_u19, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, n, ld, 1.0);
+      break;
+    case 3:
+      if (!dst) return fail(LBM_EINVAL, "U-1A needs dst");
+      hipLaunchKernelGGL(bench_u1, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, n, 1.0);
+      break;
+    default:
+      return fail(LBM_EINVAL, "unknown benchmark kind %d", kind);
+  }
+  return device_status("bench_stream");
+}
+
+}  // extern "C"

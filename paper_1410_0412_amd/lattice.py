@@ -1,0 +1,82 @@
+"""Host lattice: enumeration, adjacency list and RIA tables (C++ builder).
+
+Thin wrapper over ``lbm_lattice_*``: the tables are built by the library and
+copied into numpy arrays on request.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _capi
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Lattice:
+    """Sparse D3Q19 lattice of a voxel mask.
+
+    mask      uint8 (nx, ny, nz), C order, nonzero = solid.
+    periodic  three booleans; outside of a non-periodic axis counts as solid.
+    order     "lex" (lexicographic, x slowest) or "morton".
+    block     LS blocking factor B (0 or 1: none).
+    """
+
+    def __init__(self, mask, periodic=(True, False, False), order="lex", block=0):
+        L = _capi.lib()
+        m = np.ascontiguousarray(np.asarray(mask), dtype=np.uint8)
+        if m.ndim != 3:
+            raise ValueError("mask must be 3-D")
+        self.shape = tuple(int(s) for s in m.shape)
+        self.periodic = tuple(bool(p) for p in periodic)
+        self.order = order
+        self.block = int(block)
+        pmask = sum(1 << a for a in range(3) if self.periodic[a])
+        h = ctypes.c_void_p()
+        _capi.check(L.lbm_lattice_build(_ptr(m), *self.shape, pmask, _capi.ORDERS[order],
+                                        self.block, ctypes.byref(h)))
+        self._h = h
+        n, r, w = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _capi.check(L.lbm_lattice_sizes(h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(w)))
+        self.n_fluid, self.n_runs, self.n_waves = n.value, r.value, w.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _capi.lib().lbm_lattice_free(h)
+            self._h = None
+
+    def node_voxel(self):
+        out = np.empty(self.n_fluid, dtype=np.int32)
+        _capi.check(_capi.lib().lbm_lattice_copy_nodes(self._h, _ptr(out)))
+        return out
+
+    def adjacency(self, ld=None):
+        """int32 (18, ld): entry of direction q at row q-1."""
+        ld = self.n_fluid if ld is None else int(ld)
+        out = np.empty((18, ld), dtype=np.int32)
+        _capi.check(_capi.lib().lbm_lattice_copy_adjacency(self._h, _ptr(out), ld))
+        return out
+
+    def run_start(self):
+        out = np.empty(self.n_runs + 1, dtype=np.int32)
+        _capi.check(_capi.lib().lbm_lattice_copy_runs(self._h, _ptr(out)))
+        return out
+
+    def wave_tables(self, ldr=None):
+        """(run_delta int32 (18, ldr), head_bits uint64 (W,), run_base int32 (W,))."""
+        ldr = self.n_runs if ldr is None else int(ldr)
+        delta = np.empty((18, ldr), dtype=np.int32)
+        bits = np.empty(self.n_waves, dtype=np.uint64)
+        base = np.empty(self.n_waves, dtype=np.int32)
+        _capi.check(_capi.lib().lbm_lattice_copy_wave_tables(self._h, _ptr(delta), ldr, _ptr(bits),
+                                                             _ptr(base)))
+        return delta, bits, base
+
+    @property
+    def runs_per_node(self):
+        return self.n_runs / max(self.n_fluid, 1)

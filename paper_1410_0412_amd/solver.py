@@ -1,0 +1,165 @@
+"""Device solver: PDF grids and lattice tables in torch device memory, every
+step run by the HIP kernels of ``liblbm_sparse.so`` (``lbm_solver_*``).
+
+torch provides device memory and the current HIP stream only; no arithmetic
+of the method runs in Python.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _capi
+
+
+def _round_up(x, m):
+    return (int(x) + m - 1) // m * m
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """D3Q19 BGK solver on a :class:`Lattice`.
+
+    pattern    "aa" (one grid) or "osnt" (two grids, pull).
+    ria        True: RIA wave tables; False: adjacency list.
+    precision  "f64" (FP64 storage and arithmetic).
+    xcd_remap  sweep contiguous tile ranges per XCD (default on).
+    """
+
+    def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria=True,
+                 precision="f64", rho0=1.0, device=None, xcd_remap=True):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a GPU (HIP device); none is visible")
+        self.torch = torch
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.lattice = lattice
+        self.pattern = pattern
+        self.ria = bool(ria)
+        self.precision = precision
+        N, R = lattice.n_fluid, lattice.n_runs
+        self.n_fluid = N
+        self.ldf = _round_up(max(N, 1), 64)
+        dtype = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[precision]
+        ngrids = 2 if pattern == "osnt" else 1
+        dev = self.device
+        with torch.cuda.device(dev):
+            self.pdf = [torch.empty(19 * self.ldf, dtype=dtype, device=dev) for _ in range(ngrids)]
+            self.adj = self.run_delta = self.head_bits = self.run_base = None
+            lda = ldr = 0
+            if self.ria:
+                ldr = _round_up(max(R, 1), 64)
+                delta, bits, base = lattice.wave_tables(ldr)
+                self.run_delta = torch.from_numpy(delta).to(dev)
+                self.head_bits = torch.from_numpy(bits.view(np.int64)).to(dev)
+                self.run_base = torch.from_numpy(base).to(dev)
+            else:
+                lda = _round_up(max(N, 1), 64)
+                self.adj = torch.from_numpy(lattice.adjacency(lda)).to(dev)
+            p = _capi.Params()
+            p.tau = float(tau)
+            for a in range(3):
+                p.force[a] = float(force[a])
+            p.rho0 = float(rho0)
+            p.pattern = _capi.PATTERNS[pattern]
+            p.ria = int(self.ria)
+            p.precision = _capi.PRECISIONS[precision]
+            p.flags = 0 if xcd_remap else _capi.FLAG_NO_XCD_REMAP
+            p.n_fluid, p.n_runs, p.ldf, p.lda, p.ldr = N, R, self.ldf, lda, ldr
+            self._params = p
+            b = _capi.Buffers()
+            b.pdf[0] = self.pdf[0].data_ptr()
+            b.pdf[1] = self.pdf[1].data_ptr() if ngrids == 2 else None
+            b.adj = self.adj.data_ptr() if self.adj is not None else None
+            b.run_delta = self.run_delta.data_ptr() if self.ria else None
+            b.head_bits = self.head_bits.data_ptr() if self.ria else None
+            b.run_base = self.run_base.data_ptr() if self.ria else None
+            self._buffers = b
+            L = _capi.lib()
+            nbytes = ctypes.c_int64()
+            _capi.check(L.lbm_solver_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)))
+            self.workspace = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=dev)
+            h = ctypes.c_void_p()
+            _capi.check(L.lbm_solver_create(ctypes.byref(p), ctypes.byref(b),
+                                            _vp(self.workspace), self.workspace.numel(),
+                                            ctypes.c_void_p(self._stream()), ctypes.byref(h)))
+            self._h = h
+
+    # ------------------------------------------------------------------
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def _call(self, fn, *args):
+        L = _capi.lib()
+        with self.torch.cuda.device(self.device):
+            _capi.check(L.lbm_solver_set_stream(self._h, ctypes.c_void_p(self._stream())))
+            _capi.check(fn(self._h, *args))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _capi.lib().lbm_solver_free(h)
+            self._h = None
+
+    # ------------------------------------------------------------------
+    def _dev(self, t, shape):
+        if t is None:
+            return None
+        t = self.torch.as_tensor(t, dtype=self.torch.float64, device=self.device).contiguous()
+        if tuple(t.shape) != shape:
+            raise ValueError("expected shape %r, got %r" % (shape, tuple(t.shape)))
+        return t
+
+    def init(self, rho=None, u=None):
+        """f(0) = feq(rho, u); rho (N,), u (3, N) in node order (None: rest state)."""
+        N = self.n_fluid
+        r = self._dev(rho, (N,))
+        v = self._dev(u, (3, N))
+        self._call(_capi.lib().lbm_solver_init_equilibrium, _vp(r), _vp(v))
+        self._keep = (r, v)  # alive until the queued kernel has run
+
+    def step(self, n=1):
+        self._call(_capi.lib().lbm_solver_step, int(n))
+
+    @property
+    def t(self):
+        out = ctypes.c_int64()
+        _capi.check(_capi.lib().lbm_solver_time(self._h, ctypes.byref(out)))
+        return out.value
+
+    def moments(self):
+        """(rho (N,), u (3, N), totals (4,) = mass, jx, jy, jz) of f(t), float64."""
+        torch = self.torch
+        N = self.n_fluid
+        rho = torch.empty(N, dtype=torch.float64, device=self.device)
+        u = torch.empty((3, N), dtype=torch.float64, device=self.device)
+        tot = torch.empty(4, dtype=torch.float64, device=self.device)
+        self._call(_capi.lib().lbm_solver_moments, _vp(rho), _vp(u), _vp(tot))
+        return rho, u, tot
+
+    def export_pdfs(self):
+        """f(t) in natural order, float64 (19, N)."""
+        f = self.torch.empty((19, self.n_fluid), dtype=self.torch.float64, device=self.device)
+        self._call(_capi.lib().lbm_solver_export_pdfs, _vp(f))
+        return f
+
+    def import_pdfs(self, f, t=0):
+        g = self._dev(f, (19, self.n_fluid))
+        self._call(_capi.lib().lbm_solver_import_pdfs, _vp(g), int(t))
+        self._keep = (g,)
+
+
+def bench_stream(kind, src, dst, n, ld=0):
+    """Queue one bandwidth micro-benchmark kernel on torch's current stream."""
+    import torch
+
+    _capi.check(_capi.lib().lbm_bench_stream(int(kind), _vp(src), _vp(dst), int(n), int(ld),
+                                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))

@@ -1,0 +1,133 @@
+"""GPU parity: the HIP path against the FP64 oracle, through the C ABI.
+
+FP64 kernels evaluate the collision in the oracle's order without
+contraction, so results are expected to be bitwise identical; the stated
+bound is the normwise relative velocity error 1e-12 after 100 steps.
+"""
+import numpy as np
+import pytest
+
+from lbm_inputs import rsa_spheres, init_fields, channel_mask, relaxed_spheres, workload
+from oracle import dense
+from tests.gpu_util import solver_for, node_fields, oracle_at_nodes, normwise_u_error, VARIANTS
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+PER = (True, False, False)
+
+
+@pytest.fixture(scope="module")
+def spheres32():
+    mask, p = workload("spheres-32", seed=0)
+    f = dense.run(mask.astype(bool), p["periodic"], p["tau"], p["force"], p["steps"])
+    rho, u = dense.macroscopic(f)
+    return mask, p, f, rho, u
+
+
+@pytest.mark.parametrize("pattern,ria", VARIANTS)
+def test_spheres32_100_steps(spheres32, pattern, ria):
+    mask, p, f_ref, rho_ref, u_ref = spheres32
+    print("case spheres-32", pattern, "ria" if ria else "ia", flush=True)
+    lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], pattern, ria)
+    s.init()
+    s.step(p["steps"])
+    rho, u, tot = s.moments()
+    nv = lat.node_voxel().astype(np.int64)
+    ur = np.stack([u_ref[a].reshape(-1)[nv] for a in range(3)])
+    err = normwise_u_error(u.cpu().numpy(), ur)
+    assert err <= 1e-12, err
+    # exact: same IEEE operations in the same order
+    assert np.array_equal(u.cpu().numpy(), ur)
+    assert np.array_equal(rho.cpu().numpy(), rho_ref.reshape(-1)[nv])
+    assert np.array_equal(s.export_pdfs().cpu().numpy(), oracle_at_nodes(lat, f_ref))
+    mass_ref = rho_ref.reshape(-1)[nv].sum()
+    assert abs(tot[0].item() - mass_ref) / mass_ref < 1e-13
+
+
+@pytest.mark.parametrize("pattern,ria", VARIANTS)
+@pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 4), ("morton", 0)])
+def test_every_step_random_state(pattern, ria, order, block):
+    # non-trivial seeded initial state; all PDFs compared after every step, so
+    # both AA parities and every slot of the layouts are exercised
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.25, PER, seed=5)
+    rho0, u0 = init_fields(mask.shape, seed=6)
+    tau, F = 0.65, (2e-5, -1e-5, 5e-6)
+    print("case random-state", pattern, ria, order, block, flush=True)
+    lat, s = solver_for(mask, PER, tau, F, pattern, ria, order, block)
+    r, v = node_fields(lat, rho0, u0)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    f = dense.initial_state(mask.astype(bool), rho0, u0)
+    assert np.array_equal(s.export_pdfs().cpu().numpy(), oracle_at_nodes(lat, f))
+    for t in range(1, 8):
+        s.step(1)
+        f = dense.step(f, mask.astype(bool), PER, tau, F)
+        assert s.t == t
+        assert np.array_equal(s.export_pdfs().cpu().numpy(), oracle_at_nodes(lat, f)), t
+
+
+@pytest.mark.parametrize("pattern,ria", VARIANTS)
+def test_import_export_roundtrip(pattern, ria):
+    mask = rsa_spheres((16, 16, 16), 2.0, 0.2, PER, seed=7)
+    rho0, u0 = init_fields(mask.shape, seed=8)
+    lat, s = solver_for(mask, PER, 0.8, (1e-5, 0, 0), pattern, ria)
+    f0 = oracle_at_nodes(lat, dense.initial_state(mask.astype(bool), rho0, u0))
+    for t in (0, 1, 6, 7):
+        s.import_pdfs(torch.from_numpy(f0).cuda(), t)
+        assert s.t == t
+        assert np.array_equal(s.export_pdfs().cpu().numpy(), f0)
+    # continue from an odd time step and compare with the oracle
+    s.import_pdfs(torch.from_numpy(f0).cuda(), 3)
+    s.step(3)
+    f = dense.initial_state(mask.astype(bool), rho0, u0)
+    for _ in range(3):
+        f = dense.step(f, mask.astype(bool), PER, 0.8, (1e-5, 0, 0))
+    assert np.array_equal(s.export_pdfs().cpu().numpy(), oracle_at_nodes(lat, f))
+
+
+@pytest.mark.parametrize("shape,periodic", [((1, 1, 1), (True, True, True)), ((3, 1, 1), (True, False, False)),
+                                            ((5, 4, 3), (True, True, True)), ((7, 9, 11), (False, False, False)),
+                                            ((64, 1, 1), (True, True, True)), ((65, 3, 2), (True, False, True))])
+@pytest.mark.parametrize("pattern,ria", VARIANTS)
+def test_small_and_ragged(shape, periodic, pattern, ria):
+    rng = np.random.default_rng(sum(shape))
+    mask = (rng.random(shape) < 0.2).astype(np.uint8)
+    mask.reshape(-1)[0] = 0
+    rho0, u0 = init_fields(shape, seed=9)
+    lat, s = solver_for(mask, periodic, 0.9, (1e-5, 2e-5, -1e-5), pattern, ria)
+    r, v = node_fields(lat, rho0, u0)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    s.step(5)
+    f = dense.run(mask.astype(bool), periodic, 0.9, (1e-5, 2e-5, -1e-5), 5, rho0, u0)
+    assert np.array_equal(s.export_pdfs().cpu().numpy(), oracle_at_nodes(lat, f))
+
+
+@pytest.mark.parametrize("pattern,ria", VARIANTS)
+def test_empty_lattice(pattern, ria):
+    from paper_1410_0412_amd import Lattice, Solver
+    lat = Lattice(np.ones((4, 4, 4), np.uint8))
+    s = Solver(lat, 0.8, (1e-6, 0, 0), pattern=pattern, ria=ria)
+    s.init()
+    s.step(3)
+    rho, u, tot = s.moments()
+    assert rho.numel() == 0 and s.t == 3 and float(tot.abs().sum()) == 0.0
+
+
+def test_rest_state_and_no_remap():
+    mask = rsa_spheres((24, 24, 24), 3.0, 0.2, PER, seed=10)
+    for remap in (True, False):
+        lat, s = solver_for(mask, PER, 0.8, (0, 0, 0), "aa", True, xcd_remap=remap)
+        s.init()
+        s.step(20)
+        f = s.export_pdfs().cpu().numpy()
+        w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+        assert np.max(np.abs(f - w[:, None])) < 1e-15
+
+
+def test_errors_from_host():
+    from paper_1410_0412_amd import Lattice, Solver, LbmError
+    lat = Lattice(np.zeros((4, 4, 4), np.uint8), (True, True, True))
+    with pytest.raises(LbmError):
+        Solver(lat, 0.5)
+    with pytest.raises(LbmError):
+        Solver(lat, float("nan"))
