@@ -171,21 +171,23 @@ def main():
     r = R / N
     log("lattice N=%d R=%d r=%.4f built in %.2fs" % (N, R, r, t_build))
 
-    variants = [("aa", True, "f64")]
+    variants = [("aa", True, "f64"), ("aa", True, "f32")]
     if not args.no_variants:
-        variants += [("aa", False, "f64"), ("osnt", False, "f64"), ("osnt", True, "f64")]
+        variants += [("aa", False, "f64"), ("osnt", False, "f64"), ("osnt", True, "f64"),
+                     ("aa", True, "f16")]
     res = {}
     for pattern, ria, prec in variants:
         key = "%s_%s_%s" % (pattern, "ria" if ria else "ia", prec)
         log("timing", key)
         wall, d_a, d_b = time_variant(torch, lat, p, pattern, ria, prec, args.steps, args.warmup)
         mflups = 2 * N * args.steps / wall / 1e6
+        sb = {"f64": 8, "f32": 4, "f16": 2}[prec]
         if pattern == "aa":
             kinds = ("even", "odd_ria" if ria else "odd_ia")
-            avg = (kernel_bytes(kinds[0], N, R, W) + kernel_bytes(kinds[1], N, R, W)) / 2
+            avg = (kernel_bytes(kinds[0], N, R, W, sb) + kernel_bytes(kinds[1], N, R, W, sb)) / 2
         else:
             kinds = ("osnt_ria" if ria else "osnt_ia",) * 2
-            avg = kernel_bytes(kinds[0], N, R, W)
+            avg = kernel_bytes(kinds[0], N, R, W, sb)
         bl = avg / N
         res[key] = {
             "mflups": round(mflups, 1),

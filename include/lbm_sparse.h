@@ -56,6 +56,9 @@ enum {
 enum { LBM_ORDER_LEX = 0, LBM_ORDER_MORTON = 1 };
 enum { LBM_PATTERN_AA = 0, LBM_PATTERN_OSNT = 1 };
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
+/* Solver flag: launch the AA odd step in plain tile order instead of giving
+ * each XCD one contiguous range of tiles. */
+enum { LBM_FLAG_NO_XCD_REMAP = 1 };
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* lbm_last_error(void);
@@ -131,23 +134,29 @@ void lbm_lattice_free(lbm_lattice* lat);
 typedef struct lbm_params {
   double tau;        /* BGK relaxation time, > 1/2                           */
   double force[3];   /* constant body-force density F                       */
-  double rho0;       /* reference density of deviation storage (F32/F16)    */
+  double rho0;       /* reference density of deviation storage (> 0)        */
   int32_t pattern;   /* LBM_PATTERN_AA or LBM_PATTERN_OSNT                   */
   int32_t ria;       /* 0: adjacency list; 1: RIA wave tables                */
-  int32_t precision; /* LBM_F64 (FP64 storage and arithmetic), LBM_F32 or
-                        LBM_F16 (storage of f_q - w_q*rho0, FP32 arithmetic) */
-  int32_t flags;     /* reserved, must be 0                                  */
+  int32_t precision; /* LBM_F64: FP64 storage and arithmetic. LBM_F32: the
+                        grid stores d_q = f_q - w_q*rho0 in FP32. LBM_F16: it
+                        stores d_q * 2^f16_scale_log2 / w_q in FP16. Both
+                        deviation formats collide in FP32; moments, totals and
+                        export/import are FP64.                              */
+  int32_t flags;     /* LBM_FLAG_NO_XCD_REMAP, or 0                          */
   int64_t n_fluid;   /* N                                                    */
   int64_t n_runs;    /* R (RIA only)                                         */
   int64_t ldf;       /* elements between direction streams, >= N, multiple
-                        of 64                                                */
+                        of 64, 19*ldf <= 2^31 - 1                            */
   int64_t lda;       /* adjacency row stride (>= N), adjacency only          */
   int64_t ldr;       /* run_delta row stride (>= R), RIA only                */
+  int32_t f16_scale_log2; /* FP16 storage scale exponent s, in [-24, 24]     */
+  int32_t reserved;  /* must be 0                                            */
 } lbm_params;
 
 typedef struct lbm_buffers {
   void* pdf[2];               /* device PDF grids, 19*ldf elements of the
-                                 storage type each; pdf[1] only for OS-NT    */
+                                 storage type (double, float or IEEE half)
+                                 each; pdf[1] only for OS-NT                 */
   const int32_t* adj;         /* device [18][lda] (ria = 0)                  */
   const int32_t* run_delta;   /* device [18][ldr] (ria = 1)                  */
   const uint64_t* head_bits;  /* device [W]       (ria = 1)                  */

@@ -45,6 +45,8 @@ class Params(ctypes.Structure):
         ("ldf", ctypes.c_int64),
         ("lda", ctypes.c_int64),
         ("ldr", ctypes.c_int64),
+        ("f16_scale_log2", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

@@ -39,12 +39,14 @@ constexpr double kW[Q] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 
 
 // Per-launch collision constants (host-computed, passed by value).
 struct Collision {
-  double omega;     // 1 / tau
-  double S[Q];      // 3 w_q (c_q . F)
+  double omega;      // 1 / tau
+  double S[Q];       // 3 w_q (c_q . F)
+  double rho0;       // reference density of deviation storage
   float omega_f;
   float S_f[Q];
-  float rho0_f;     // reference density of deviation storage
-  float pad_;
+  float rho0_f;
+  float h_scale[Q];    // FP16 storage: stored value = deviation * h_scale[q]
+  float h_unscale[Q];  // 1 / h_scale[q] (exact: powers of two times 1/3, 1/18, 1/36)
 };
 
 // c_q . v folded over the nonzero components of c_q in axis order.
@@ -115,5 +117,83 @@ __device__ __forceinline__ void collide_f64(double (&f)[Q], const Collision& c) 
     f[q] = (f[q] - c.omega * (f[q] - feq)) + c.S[q];
   }
 }
+
+// ------------------------------------------------------------------------
+// Deviation storage: the grid holds d_q = f_q - w_q rho0 (FP32, or FP16
+// scaled by 2^s / w_q), arithmetic in FP32. Since sum_q w_q = 1 and
+// sum_q w_q c_q = 0, rho = rho0 + sum_q d_q and j = sum_q c_q d_q, and the
+// equilibrium deviation is w_q (drho + rho (3 cu + 9/2 cu^2 - 3/2 u.u)), so
+// the O(1) rest part never enters a rounding step.
+
+constexpr float kWf[Q] = {1.0f / 3.0f,  1.0f / 18.0f, 1.0f / 18.0f, 1.0f / 18.0f, 1.0f / 18.0f,
+                          1.0f / 18.0f, 1.0f / 18.0f, 1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f,
+                          1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f,
+                          1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f};
+
+__device__ __forceinline__ void collide_dev_f32(float (&d)[Q], const Collision& c) {
+#pragma clang fp contract(fast)
+  const float drho = density(d);
+  const float rho = c.rho0_f + drho;
+  const float jx = momentum<0>(d);
+  const float jy = momentum<1>(d);
+  const float jz = momentum<2>(d);
+  const float ir = 1.0f / rho;
+  const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const float cu = cdot<float>(q, ux, uy, uz);
+    const float deq = kWf[q] * (drho + rho * (cu * (3.0f + 4.5f * cu) - usq15));
+    d[q] = d[q] - c.omega_f * (d[q] - deq) + c.S_f[q];
+  }
+}
+
+// Deviation of the equilibrium in FP64 (initialisation of deviation storage).
+__device__ __forceinline__ double equilibrium_dev_f64(int q, double rho, double rho0, double ux,
+                                                      double uy, double uz) {
+  const double usq = (ux * ux + uy * uy) + uz * uz;
+  const double cu = cdot<double>(q, ux, uy, uz);
+  return kW[q] * ((rho - rho0) + rho * ((3.0 * cu + (4.5 * cu) * cu) - 1.5 * usq));
+}
+
+// Storage traits. value64: the stored quantity in FP64 (f_q for FP64
+// storage, the deviation d_q otherwise); from64: its rounding to storage.
+template <class S>
+struct Prec;
+
+template <>
+struct Prec<double> {
+  static constexpr bool kDeviation = false;
+  __device__ static void collide(double (&v)[Q], const Collision& c) { collide_f64(v, c); }
+  __device__ static double value64(int, double v, const Collision&) { return v; }
+  __device__ static double from64(int, double x, const Collision&) { return x; }
+};
+
+template <>
+struct Prec<float> {
+  static constexpr bool kDeviation = true;
+  __device__ static void collide(float (&v)[Q], const Collision& c) { collide_dev_f32(v, c); }
+  __device__ static double value64(int, float v, const Collision&) { return (double)v; }
+  __device__ static float from64(int, double d, const Collision&) { return (float)d; }
+};
+
+template <>
+struct Prec<_Float16> {
+  static constexpr bool kDeviation = true;
+  __device__ static void collide(_Float16 (&v)[Q], const Collision& c) {
+    float d[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) d[q] = (float)v[q] * c.h_unscale[q];
+    collide_dev_f32(d, c);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = (_Float16)(d[q] * c.h_scale[q]);
+  }
+  __device__ static double value64(int q, _Float16 v, const Collision& c) {
+    return (double)v * (double)c.h_unscale[q];
+  }
+  __device__ static _Float16 from64(int q, double d, const Collision& c) {
+    return (_Float16)(float)(d * (double)c.h_scale[q]);
+  }
+};
 
 }  // namespace lbm

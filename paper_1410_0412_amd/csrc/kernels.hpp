@@ -47,7 +47,7 @@ __device__ __forceinline__ int64_t tile_index(int remap) {
 
 struct IndexIA {
   const int32_t* __restrict__ adj;
-  int64_t lda;
+  int32_t lda;
 
   __device__ __forceinline__ void get(int32_t n, int32_t (&a)[18]) const {
 #pragma unroll
@@ -59,7 +59,7 @@ struct IndexRIA {
   const int32_t* __restrict__ delta;
   const uint64_t* __restrict__ head_bits;
   const int32_t* __restrict__ run_base;
-  int64_t ldr;
+  int32_t ldr;
 
   __device__ __forceinline__ void get(int32_t n, int32_t (&a)[18]) const {
     // all lanes of the wave hold nodes 64w .. 64w+63
@@ -87,66 +87,90 @@ struct IndexRIA {
   }
 };
 
+// Slots are 32-bit element offsets into the grid (the host guarantees
+// 19 * ldf < 2^31). Stream offsets q * ldf are wave-uniform and kept in
+// scalar registers; per lane a slot costs one compare, two selects and one
+// add, with no branch.
+__device__ __forceinline__ int32_t stream_offset(int q, int32_t ldf) {
+  return __builtin_amdgcn_readfirstlane(q * ldf);
+}
+
+__device__ __forceinline__ int32_t select_slot(int32_t an, int32_t n, int32_t base_fluid,
+                                               int32_t base_wall) {
+  const bool fluid = an >= 0;
+  const int32_t idx = fluid ? an : n;
+  const int32_t base = fluid ? base_fluid : base_wall;
+  return base + idx;
+}
+
 // AA odd-step slot of f_q for node n: L_q(n).
-__device__ __forceinline__ int64_t aa_slot(int q, int32_t n, const int32_t (&a)[18], int64_t ldf) {
+__device__ __forceinline__ int32_t aa_slot(int q, int32_t n, const int32_t (&a)[18], int32_t ldf) {
   if (q == 0) return n;
-  const int32_t an = a[q - 1];
-  return an >= 0 ? (int64_t)kOpp[q] * ldf + an : (int64_t)q * ldf + n;
+  return select_slot(a[q - 1], n, stream_offset(kOpp[q], ldf), stream_offset(q, ldf));
 }
 
 // OS-NT pull slot of f_q for node n.
-__device__ __forceinline__ int64_t pull_slot(int q, int32_t n, const int32_t (&a)[18], int64_t ldf) {
+__device__ __forceinline__ int32_t pull_slot(int q, int32_t n, const int32_t (&a)[18], int32_t ldf) {
   if (q == 0) return n;
-  const int32_t an = a[q - 1];
-  return an >= 0 ? (int64_t)q * ldf + an : (int64_t)kOpp[q] * ldf + n;
+  return select_slot(a[q - 1], n, stream_offset(q, ldf), stream_offset(kOpp[q], ldf));
 }
 
-// ------------------------------------------------------------ FP64 steps --
+// ------------------------------------------------------------- step kernels --
+// S is the storage type: double (FP64 arithmetic in the oracle's order),
+// float or _Float16 (deviation storage, FP32 arithmetic).
 
+template <class S>
 __global__ void __launch_bounds__(kBlock)
-aa_even_f64(double* __restrict__ F, int32_t N, int64_t ldf, Collision c, int remap) {
+aa_even(S* __restrict__ F, int32_t N, int32_t ldf, Collision c, int remap) {
   const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  double f[Q];
+  S f[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = __builtin_nontemporal_load(F + q * ldf + n);
-  collide_f64(f, c);
+  for (int q = 0; q < Q; ++q) f[q] = __builtin_nontemporal_load(F + (stream_offset(q, ldf) + n));
+  Prec<S>::collide(f, c);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], F + kOpp[q] * ldf + n);
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], F + (stream_offset(kOpp[q], ldf) + n));
 }
 
-template <class Idx>
+template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-aa_odd_f64(double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, Collision c, int remap) {
-  const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
-  if (n64 >= N) return;
-  const int32_t n = (int32_t)n64;
-  int32_t a[18];
-  idx.get(n, a);
-  double f[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = F[aa_slot(q, n, a, ldf)];
-  collide_f64(f, c);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) F[aa_slot(kOpp[q], n, a, ldf)] = f[q];
-}
-
-template <class Idx>
-__global__ void __launch_bounds__(kBlock)
-osnt_f64(const double* __restrict__ G, double* __restrict__ H, int32_t N, int64_t ldf, Idx idx,
-         Collision c, int remap) {
+aa_odd(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, Collision c, int remap) {
   const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t a[18];
   idx.get(n, a);
-  double f[Q];
+  int32_t slot[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = G[pull_slot(q, n, a, ldf)];
-  collide_f64(f, c);
+  for (int q = 0; q < Q; ++q) slot[q] = aa_slot(q, n, a, ldf);
+  S f[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], H + q * ldf + n);
+  for (int q = 0; q < Q; ++q) f[q] = F[slot[q]];
+  Prec<S>::collide(f, c);
+  // f*_q goes where f_qbar came from
+#pragma unroll
+  for (int q = 0; q < Q; ++q) F[slot[kOpp[q]]] = f[q];
+}
+
+template <class S, class Idx>
+__global__ void __launch_bounds__(kBlock)
+osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, int32_t ldf, Idx idx, Collision c,
+     int remap) {
+  const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
+  if (n64 >= N) return;
+  const int32_t n = (int32_t)n64;
+  int32_t a[18];
+  idx.get(n, a);
+  int32_t slot[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) slot[q] = pull_slot(q, n, a, ldf);
+  S f[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) f[q] = G[slot[q]];
+  Prec<S>::collide(f, c);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], H + (stream_offset(q, ldf) + n));
 }
 
 }  // namespace lbm

@@ -5,8 +5,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -34,11 +36,11 @@ constexpr int kRedBlocks = 1024;  // fixed grid of the reduction: deterministic 
 enum Layout : int { kNatural = 0, kAAOdd = 1, kPull = 2 };
 
 template <class Idx>
-__device__ __forceinline__ void state_slots(int layout, int32_t n, const Idx& idx, int64_t ldf,
-                                            int64_t (&s)[Q]) {
+__device__ __forceinline__ void state_slots(int layout, int32_t n, const Idx& idx, int32_t ldf,
+                                            int32_t (&s)[Q]) {
   if (layout == kNatural) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] = (int64_t)q * ldf + n;
+    for (int q = 0; q < Q; ++q) s[q] = q * ldf + n;
     return;
   }
   int32_t a[18];
@@ -52,65 +54,79 @@ __device__ __forceinline__ void state_slots(int layout, int32_t n, const Idx& id
   }
 }
 
-template <class Idx>
+template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-init_eq_f64(double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, int layout,
-            const double* __restrict__ rho, const double* __restrict__ u, double rho0) {
+init_eq(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout,
+        const double* __restrict__ rho, const double* __restrict__ u, Collision c) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  const double r = rho ? rho[n] : rho0;
+  const double r = rho ? rho[n] : c.rho0;
   const double ux = u ? u[n] : 0.0, uy = u ? u[(int64_t)N + n] : 0.0, uz = u ? u[2 * (int64_t)N + n] : 0.0;
-  double feq[Q];
-  equilibrium_f64(r, ux, uy, uz, feq);
-  int64_t s[Q];
+  double v[Q];
+  if constexpr (Prec<S>::kDeviation) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = equilibrium_dev_f64(q, r, c.rho0, ux, uy, uz);
+  } else {
+    equilibrium_f64(r, ux, uy, uz, v);
+  }
+  int32_t s[Q];
   state_slots(layout, n, idx, ldf, s);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) F[s[q]] = feq[q];
+  for (int q = 0; q < Q; ++q) F[s[q]] = Prec<S>::from64(q, v[q], c);
 }
 
-template <class Idx>
+// f(t) in natural order, FP64.
+template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-gather_f64(const double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, int layout,
-           double* __restrict__ out) {
+gather_pdfs(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Collision c,
+            double* __restrict__ out) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  int64_t s[Q];
+  int32_t s[Q];
   state_slots(layout, n, idx, ldf, s);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) out[(int64_t)q * N + n] = F[s[q]];
+  for (int q = 0; q < Q; ++q) {
+    const double v = Prec<S>::value64(q, F[s[q]], c);
+    out[(int64_t)q * N + n] = Prec<S>::kDeviation ? kW[q] * c.rho0 + v : v;
+  }
 }
 
-template <class Idx>
+template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-scatter_f64(double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, int layout,
-            const double* __restrict__ in) {
+scatter_pdfs(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Collision c,
+             const double* __restrict__ in) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  int64_t s[Q];
+  int32_t s[Q];
   state_slots(layout, n, idx, ldf, s);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) F[s[q]] = in[(int64_t)q * N + n];
+  for (int q = 0; q < Q; ++q) {
+    const double f = in[(int64_t)q * N + n];
+    F[s[q]] = Prec<S>::from64(q, Prec<S>::kDeviation ? f - kW[q] * c.rho0 : f, c);
+  }
 }
 
-// rho, u = j / rho of f(t), plus per-block partial sums of rho and j.
-template <class Idx>
+// rho, u = j / rho of f(t), plus per-block partial sums of rho and j, all in
+// FP64. FP64 storage: the oracle's folds over f. Deviation storage: folds
+// over the deviations, rho = rho0 + sum_q d_q.
+template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-moments_f64(const double* __restrict__ F, int32_t N, int64_t ldf, Idx idx, int layout,
-            double* __restrict__ rho_out, double* __restrict__ u_out, double* __restrict__ partial) {
+moments(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Collision c,
+        double* __restrict__ rho_out, double* __restrict__ u_out, double* __restrict__ partial) {
   __shared__ double red[4][kBlock];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x; n64 < N;
        n64 += (int64_t)gridDim.x * kBlock) {
     const int32_t n = (int32_t)n64;
-    int64_t s[Q];
+    int32_t s[Q];
     state_slots(layout, n, idx, ldf, s);
     double f[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = F[s[q]];
-    const double rho = density(f);
+    for (int q = 0; q < Q; ++q) f[q] = Prec<S>::value64(q, F[s[q]], c);
+    const double rho = Prec<S>::kDeviation ? c.rho0 + density(f) : density(f);
     const double jx = momentum<0>(f), jy = momentum<1>(f), jz = momentum<2>(f);
     if (rho_out) rho_out[n] = rho;
     if (u_out) {
@@ -211,9 +227,9 @@ int device_status(const char* what) {
   return LBM_OK;
 }
 
-IndexIA index_ia(const lbm_solver* s) { return IndexIA{s->b.adj, s->p.lda}; }
+IndexIA index_ia(const lbm_solver* s) { return IndexIA{s->b.adj, (int32_t)s->p.lda}; }
 IndexRIA index_ria(const lbm_solver* s) {
-  return IndexRIA{s->b.run_delta, s->b.head_bits, s->b.run_base, s->p.ldr};
+  return IndexRIA{s->b.run_delta, s->b.head_bits, s->b.run_base, (int32_t)s->p.ldr};
 }
 
 // Layout of f(t) in the current grid.
@@ -222,17 +238,24 @@ int current_layout(const lbm_solver* s) {
   return (s->t % 2 == 0) ? kNatural : kAAOdd;
 }
 
-double* current_grid(const lbm_solver* s) {
-  return (double*)s->b.pdf[s->p.pattern == LBM_PATTERN_OSNT ? s->cur : 0];
+void* current_grid(const lbm_solver* s) {
+  return s->b.pdf[s->p.pattern == LBM_PATTERN_OSNT ? s->cur : 0];
 }
 
+// Call fn(S*, idx) with the storage type and index source of the solver.
 template <class Fn>
-int with_index(const lbm_solver* s, Fn&& fn) {
-  if (s->p.ria)
-    fn(index_ria(s));
-  else
-    fn(index_ia(s));
-  return LBM_OK;
+void dispatch(const lbm_solver* s, void* grid, Fn&& fn) {
+  auto with_idx = [&](auto* typed) {
+    if (s->p.ria)
+      fn(typed, index_ria(s));
+    else
+      fn(typed, index_ia(s));
+  };
+  switch (s->p.precision) {
+    case LBM_F64: with_idx((double*)grid); break;
+    case LBM_F32: with_idx((float*)grid); break;
+    default: with_idx((_Float16*)grid); break;
+  }
 }
 
 int launch_step(lbm_solver* s) {
@@ -242,26 +265,33 @@ int launch_step(lbm_solver* s) {
     s->t += 1;
     return LBM_OK;
   }
-  unsigned grid = grid_for(N);
-  if (s->remap) grid = (grid + 7) / 8 * 8;
-  const dim3 g(grid), b(kBlock);
-  const int64_t ldf = s->p.ldf;
+  const unsigned tiles = grid_for(N);
+  const unsigned tiles8 = (tiles + 7) / 8 * 8;
+  const dim3 b(kBlock);
+  const int32_t ldf = (int32_t)s->p.ldf;
   if (s->p.pattern == LBM_PATTERN_AA) {
-    double* F = (double*)s->b.pdf[0];
     if (s->t % 2 == 0) {
-      hipLaunchKernelGGL(aa_even_f64, g, b, 0, s->stream, F, N, ldf, s->c, s->remap);
+      dispatch(s, s->b.pdf[0], [&](auto* F, auto) {
+        using S = std::remove_pointer_t<decltype(F)>;
+        hipLaunchKernelGGL(aa_even<S>, dim3(tiles), b, 0, s->stream, F, N, ldf, s->c, 0);
+      });
     } else {
-      with_index(s, [&](auto idx) {
-        hipLaunchKernelGGL(aa_odd_f64<decltype(idx)>, g, b, 0, s->stream, F, N, ldf, idx, s->c,
-                           s->remap);
+      // the scattered stores of the odd step share partial lines between
+      // neighbouring tiles: keep neighbours on one XCD
+      const int remap = s->remap;
+      dispatch(s, s->b.pdf[0], [&](auto* F, auto idx) {
+        using S = std::remove_pointer_t<decltype(F)>;
+        hipLaunchKernelGGL((aa_odd<S, decltype(idx)>), dim3(remap ? tiles8 : tiles), b, 0, s->stream,
+                           F, N, ldf, idx, s->c, remap);
       });
     }
   } else {
-    const double* G = (const double*)s->b.pdf[s->cur];
-    double* H = (double*)s->b.pdf[1 - s->cur];
-    with_index(s, [&](auto idx) {
-      hipLaunchKernelGGL(osnt_f64<decltype(idx)>, g, b, 0, s->stream, G, H, N, ldf, idx, s->c,
-                         s->remap);
+    void* G = s->b.pdf[s->cur];
+    void* H = s->b.pdf[1 - s->cur];
+    dispatch(s, G, [&](auto* Gt, auto idx) {
+      using S = std::remove_pointer_t<decltype(Gt)>;
+      hipLaunchKernelGGL((osnt<S, decltype(idx)>), dim3(tiles), b, 0, s->stream, (const S*)Gt, (S*)H, N,
+                         ldf, idx, s->c, 0);
     });
     s->cur = 1 - s->cur;
   }
@@ -274,23 +304,30 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 1/2");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->force[a])) return fail(LBM_EINVAL, "force must be finite");
+  if (!std::isfinite(p->rho0) || !(p->rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be positive");
   if (p->pattern != LBM_PATTERN_AA && p->pattern != LBM_PATTERN_OSNT)
     return fail(LBM_EINVAL, "unknown pattern %d", p->pattern);
   if (p->ria != 0 && p->ria != 1) return fail(LBM_EINVAL, "ria must be 0 or 1");
-  if (p->precision != LBM_F64) return fail(LBM_EINVAL, "precision %d is not available", p->precision);
-  if (p->flags & ~1) return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->precision != LBM_F64 && p->precision != LBM_F32 && p->precision != LBM_F16)
+    return fail(LBM_EINVAL, "unknown precision %d", p->precision);
+  if (p->flags & ~LBM_FLAG_NO_XCD_REMAP) return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->f16_scale_log2 < -24 || p->f16_scale_log2 > 24) return fail(LBM_EINVAL, "f16_scale_log2 out of [-24, 24]");
+  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
   if (p->n_fluid < 0) return fail(LBM_EINVAL, "n_fluid < 0");
   if (p->n_fluid > INT32_MAX - 64) return fail(LBM_ERANGE, "n_fluid exceeds the int32 node index");
   if (p->ldf < p->n_fluid || p->ldf % 64 != 0) return fail(LBM_EINVAL, "ldf must be >= N and a multiple of 64");
+  if (p->ldf > (int64_t)INT32_MAX / Q) return fail(LBM_ERANGE, "19 * ldf exceeds the int32 slot index");
   if (!b->pdf[0]) return fail(LBM_EINVAL, "pdf[0] is null");
   if (p->pattern == LBM_PATTERN_OSNT && !b->pdf[1]) return fail(LBM_EINVAL, "OS-NT needs pdf[1]");
   if (p->ria) {
     if (p->n_runs < 0 || (p->n_fluid > 0 && p->n_runs < 1)) return fail(LBM_EINVAL, "n_runs invalid");
     if (p->ldr < p->n_runs) return fail(LBM_EINVAL, "ldr < n_runs");
+    if (p->ldr > (int64_t)INT32_MAX / 18) return fail(LBM_ERANGE, "18 * ldr exceeds int32");
     if (p->n_fluid > 0 && (!b->run_delta || !b->head_bits || !b->run_base))
       return fail(LBM_EINVAL, "RIA needs run_delta, head_bits and run_base");
   } else {
     if (p->lda < p->n_fluid) return fail(LBM_EINVAL, "lda < n_fluid");
+    if (p->lda > (int64_t)INT32_MAX / 18) return fail(LBM_ERANGE, "18 * lda exceeds int32");
     if (p->n_fluid > 0 && !b->adj) return fail(LBM_EINVAL, "adjacency list is null");
   }
   return LBM_OK;
@@ -327,14 +364,21 @@ int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace
   s->ws = (double*)workspace;
   s->ws_bytes = workspace_bytes;
   s->stream = (hipStream_t)hip_stream;
-  s->remap = (p->flags & 1) ? 0 : 1;
-  s->c.omega = 1.0 / p->tau;
-  for (int q = 0; q < Q; ++q)
-    s->c.S[q] = (3.0 * kW[q]) * cdot<double>(q, p->force[0], p->force[1], p->force[2]);
-  s->c.omega_f = (float)s->c.omega;
-  for (int q = 0; q < Q; ++q) s->c.S_f[q] = (float)s->c.S[q];
-  s->c.rho0_f = (float)p->rho0;
-  s->c.pad_ = 0.f;
+  s->remap = (p->flags & LBM_FLAG_NO_XCD_REMAP) ? 0 : 1;
+  Collision& c = s->c;
+  c.omega = 1.0 / p->tau;
+  for (int q = 0; q < Q; ++q) c.S[q] = (3.0 * kW[q]) * cdot<double>(q, p->force[0], p->force[1], p->force[2]);
+  c.rho0 = p->rho0;
+  c.omega_f = (float)c.omega;
+  for (int q = 0; q < Q; ++q) c.S_f[q] = (float)c.S[q];
+  c.rho0_f = (float)p->rho0;
+  // FP16 stores d_q * 2^s / w_q: powers of two times 3, 18 or 36, exact in FP32
+  const float two_s = std::ldexp(1.0f, p->f16_scale_log2);
+  for (int q = 0; q < Q; ++q) {
+    const float inv_w = q == 0 ? 3.0f : (q < 7 ? 18.0f : 36.0f);
+    c.h_scale[q] = two_s * inv_w;
+    c.h_unscale[q] = 1.0f / c.h_scale[q];
+  }
   *out = s;
   return LBM_OK;
 }
@@ -354,10 +398,10 @@ int lbm_solver_init_equilibrium(lbm_solver* s, const double* rho, const double* 
   const int32_t N = (int32_t)s->p.n_fluid;
   if (N == 0) return LBM_OK;
   const int layout = s->p.pattern == LBM_PATTERN_OSNT ? kPull : kNatural;
-  double* F = (double*)s->b.pdf[0];
-  with_index(s, [&](auto idx) {
-    hipLaunchKernelGGL(init_eq_f64<decltype(idx)>, dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F,
-                       N, s->p.ldf, idx, layout, rho, u, s->p.rho0);
+  dispatch(s, s->b.pdf[0], [&](auto* F, auto idx) {
+    using S = std::remove_pointer_t<decltype(F)>;
+    hipLaunchKernelGGL((init_eq<S, decltype(idx)>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N,
+                       (int32_t)s->p.ldf, idx, layout, rho, u, s->c);
   });
   return device_status("init_equilibrium");
 }
@@ -381,20 +425,18 @@ int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals) {
   clear_error();
   if (!s) return fail(LBM_EINVAL, "null solver");
   const int32_t N = (int32_t)s->p.n_fluid;
-  if (N == 0) {
-    if (totals)  // no partials: the finishing kernel writes zeros
-      hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, s->ws, 0, totals);
-  } else {
-    const unsigned grid = std::min<unsigned>(grid_for(N), kRedBlocks);
-    const double* F = current_grid(s);
+  unsigned parts = 0;
+  if (N > 0) {
+    parts = std::min<unsigned>(grid_for(N), kRedBlocks);
     const int layout = current_layout(s);
-    with_index(s, [&](auto idx) {
-      hipLaunchKernelGGL(moments_f64<decltype(idx)>, dim3(grid), dim3(kBlock), 0, s->stream, F, N,
-                         s->p.ldf, idx, layout, rho, u, s->ws);
+    dispatch(s, current_grid(s), [&](auto* F, auto idx) {
+      using S = std::remove_pointer_t<decltype(F)>;
+      hipLaunchKernelGGL((moments<S, decltype(idx)>), dim3(parts), dim3(kBlock), 0, s->stream, (const S*)F,
+                         N, (int32_t)s->p.ldf, idx, layout, s->c, rho, u, s->ws);
     });
-    if (totals)
-      hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, s->ws, (int)grid, totals);
   }
+  if (totals)  // with no partials the finishing kernel writes zeros
+    hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, s->ws, (int)parts, totals);
   int rc = device_status("moments");
   if (rc) return rc;
   if (hipStreamSynchronize(s->stream) != hipSuccess) return device_status("moments (sync)");
@@ -406,11 +448,11 @@ int lbm_solver_export_pdfs(lbm_solver* s, double* f) {
   if (!s || !f) return fail(LBM_EINVAL, "null pointer");
   const int32_t N = (int32_t)s->p.n_fluid;
   if (N > 0) {
-    const double* F = current_grid(s);
     const int layout = current_layout(s);
-    with_index(s, [&](auto idx) {
-      hipLaunchKernelGGL(gather_f64<decltype(idx)>, dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F,
-                         N, s->p.ldf, idx, layout, f);
+    dispatch(s, current_grid(s), [&](auto* F, auto idx) {
+      using S = std::remove_pointer_t<decltype(F)>;
+      hipLaunchKernelGGL((gather_pdfs<S, decltype(idx)>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream,
+                         (const S*)F, N, (int32_t)s->p.ldf, idx, layout, s->c, f);
     });
   }
   int rc = device_status("export_pdfs");
@@ -427,11 +469,11 @@ int lbm_solver_import_pdfs(lbm_solver* s, const double* f, int64_t t) {
   s->cur = 0;
   const int32_t N = (int32_t)s->p.n_fluid;
   if (N == 0) return LBM_OK;
-  double* F = current_grid(s);
   const int layout = current_layout(s);
-  with_index(s, [&](auto idx) {
-    hipLaunchKernelGGL(scatter_f64<decltype(idx)>, dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F,
-                       N, s->p.ldf, idx, layout, f);
+  dispatch(s, current_grid(s), [&](auto* F, auto idx) {
+    using S = std::remove_pointer_t<decltype(F)>;
+    hipLaunchKernelGGL((scatter_pdfs<S, decltype(idx)>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F,
+                       N, (int32_t)s->p.ldf, idx, layout, s->c, f);
   });
   return device_status("import_pdfs");
 }

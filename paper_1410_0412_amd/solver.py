@@ -22,17 +22,43 @@ def _vp(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+_STREAM_ALIGN = 2 << 20  # bytes
+
+
+def grid_stride(n, elem_bytes):
+    """Elements between direction streams: >= n, a multiple of 64, and for
+    large grids a multiple of 2 MiB, so every stream starts on a 2 MiB
+    boundary (the GPU counterpart of the paper's padding against cache and
+    TLB thrashing, Sect. 4.3)."""
+    ld = _round_up(max(n, 1), 64)
+    big = _round_up(ld, _STREAM_ALIGN // elem_bytes)
+    if 8 * (big - ld) <= ld and 19 * big <= 2 ** 31 - 1:  # at most 12.5% padding
+        return big
+    return ld
+
+
+def aligned_empty(torch, numel, dtype, device, align=_STREAM_ALIGN):
+    """A 1-D tensor of ``numel`` elements whose first element is ``align``-aligned."""
+    esize = torch.empty((), dtype=dtype).element_size()
+    extra = align // esize
+    base = torch.empty(numel + extra, dtype=dtype, device=device)
+    off = (-base.data_ptr() % align) // esize
+    return base[off:off + numel]
+
+
 class Solver:
     """D3Q19 BGK solver on a :class:`Lattice`.
 
     pattern    "aa" (one grid) or "osnt" (two grids, pull).
     ria        True: RIA wave tables; False: adjacency list.
-    precision  "f64" (FP64 storage and arithmetic).
-    xcd_remap  sweep contiguous tile ranges per XCD (default on).
+    precision  "f64" (FP64 storage and arithmetic), "f32" or "f16"
+               (storage of deviations from the rest state, FP32 arithmetic).
+    f16_scale_log2  FP16 storage holds d_q * 2^s / w_q (default s = 10).
+    xcd_remap  AA odd step: each XCD sweeps one contiguous tile range.
     """
 
     def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria=True,
-                 precision="f64", rho0=1.0, device=None, xcd_remap=True):
+                 precision="f64", rho0=1.0, device=None, xcd_remap=True, f16_scale_log2=10):
         import torch
 
         if not torch.cuda.is_available():
@@ -47,12 +73,12 @@ class Solver:
         self.precision = precision
         N, R = lattice.n_fluid, lattice.n_runs
         self.n_fluid = N
-        self.ldf = _round_up(max(N, 1), 64)
         dtype = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[precision]
+        self.ldf = grid_stride(N, torch.empty((), dtype=dtype).element_size())
         ngrids = 2 if pattern == "osnt" else 1
         dev = self.device
         with torch.cuda.device(dev):
-            self.pdf = [torch.empty(19 * self.ldf, dtype=dtype, device=dev) for _ in range(ngrids)]
+            self.pdf = [aligned_empty(torch, 19 * self.ldf, dtype, dev) for _ in range(ngrids)]
             self.adj = self.run_delta = self.head_bits = self.run_base = None
             lda = ldr = 0
             if self.ria:
@@ -74,6 +100,7 @@ class Solver:
             p.precision = _capi.PRECISIONS[precision]
             p.flags = 0 if xcd_remap else _capi.FLAG_NO_XCD_REMAP
             p.n_fluid, p.n_runs, p.ldf, p.lda, p.ldr = N, R, self.ldf, lda, ldr
+            p.f16_scale_log2 = int(f16_scale_log2)
             self._params = p
             b = _capi.Buffers()
             b.pdf[0] = self.pdf[0].data_ptr()

@@ -1,0 +1,109 @@
+"""Deviation storage (FP32 and FP16 PDFs, FP32 arithmetic, FP64 moments and
+reductions) against the FP64 oracle, error stated per field.
+
+Tolerances (derived in the design notes from the unit roundoff of the storage
+format and the step count): FP32 normwise velocity error <= 1e-5, density
+<= 1e-7 absolute, mass <= 1e-9 relative; FP16 (relative precision 2^-11)
+normwise velocity error <= 5e-3, density <= 5e-5, mass <= 1e-6.
+"""
+import numpy as np
+import pytest
+
+from lbm_inputs import rsa_spheres, init_fields, workload
+from oracle import dense
+from tests.gpu_util import solver_for, node_fields, normwise_u_error, VARIANTS
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+PER = (True, False, False)
+TOL = {"f32": dict(u=1e-5, rho=1e-7, mass=1e-9), "f16": dict(u=5e-3, rho=5e-5, mass=1e-6)}
+
+
+def field_errors(lat, s, f_ref):
+    rho, u, tot = s.moments()
+    nv = lat.node_voxel().astype(np.int64)
+    r_ref, u_ref = dense.macroscopic(f_ref)
+    rr = r_ref.reshape(-1)[nv]
+    ur = np.stack([u_ref[a].reshape(-1)[nv] for a in range(3)])
+    return dict(
+        u=normwise_u_error(u.cpu().numpy(), ur),
+        rho=float(np.max(np.abs(rho.cpu().numpy() - rr))),
+        mass=abs(tot[0].item() - rr.sum()) / rr.sum(),
+        ux=float(np.max(np.abs(u[0].cpu().numpy() - ur[0])) / np.max(np.abs(ur[0]))),
+    )
+
+
+@pytest.fixture(scope="module")
+def spheres32():
+    mask, p = workload("spheres-32", seed=0)
+    f = dense.run(mask.astype(bool), p["periodic"], p["tau"], p["force"], p["steps"])
+    return mask, p, f
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_spheres32_forced_flow(spheres32, prec):
+    mask, p, f_ref = spheres32
+    lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], "aa", True, precision=prec)
+    s.init()
+    s.step(p["steps"])
+    e = field_errors(lat, s, f_ref)
+    print("spheres-32 %s errors %r" % (prec, e), flush=True)
+    for k, tol in TOL[prec].items():
+        assert e[k] <= tol, (k, e[k])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_random_state(prec):
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.25, PER, seed=5)
+    rho0, u0 = init_fields(mask.shape, seed=6)
+    tau, F = 0.65, (2e-5, -1e-5, 5e-6)
+    lat, s = solver_for(mask, PER, tau, F, "aa", True, precision=prec)
+    r, v = node_fields(lat, rho0, u0)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    s.step(40)
+    f = dense.run(mask.astype(bool), PER, tau, F, 40, rho0, u0)
+    e = field_errors(lat, s, f)
+    print("random-state %s errors %r" % (prec, e), flush=True)
+    for k, tol in TOL[prec].items():
+        assert e[k] <= tol, (k, e[k])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_variants_bitwise_identical(prec):
+    # the arithmetic per node does not depend on addressing or pattern
+    mask = rsa_spheres((24, 20, 18), 2.5, 0.25, PER, seed=7)
+    rho0, u0 = init_fields(mask.shape, seed=8)
+    outs = []
+    for pattern, ria in VARIANTS:
+        lat, s = solver_for(mask, PER, 0.7, (1e-5, 0, 0), pattern, ria, precision=prec)
+        r, v = node_fields(lat, rho0, u0)
+        s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+        s.step(11)
+        outs.append(s.export_pdfs().cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_import_export_roundtrip(prec):
+    mask = rsa_spheres((12, 12, 12), 2.0, 0.2, PER, seed=9)
+    rho0, u0 = init_fields(mask.shape, seed=10)
+    lat, s = solver_for(mask, PER, 0.8, (0, 0, 0), "aa", True, precision=prec)
+    r, v = node_fields(lat, rho0, u0)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    f0 = s.export_pdfs()
+    for t in (0, 1, 4, 5):
+        s.import_pdfs(f0, t)
+        assert np.array_equal(s.export_pdfs().cpu().numpy(), f0.cpu().numpy())
+
+
+def test_rest_state_exact():
+    # deviations of the rest state are exactly zero in every format
+    mask = rsa_spheres((16, 16, 16), 2.5, 0.2, PER, seed=11)
+    for prec in ("f32", "f16"):
+        lat, s = solver_for(mask, PER, 0.8, (0, 0, 0), "aa", True, precision=prec)
+        s.init()
+        s.step(10)
+        rho, u, tot = s.moments()
+        assert float(u.abs().max()) == 0.0 and float((rho - 1).abs().max()) == 0.0
