@@ -53,9 +53,10 @@ enum {
   LBM_ESTATE = -5   /* call not valid in the object's current state        */
 };
 
-enum { LBM_ORDER_LEX = 0, LBM_ORDER_MORTON = 1 };
+enum { LBM_ORDER_LEX = 0, LBM_ORDER_MORTON = 1, LBM_ORDER_HILBERT = 2, LBM_ORDER_HILBERT_LS = 3 };
 enum { LBM_PATTERN_AA = 0, LBM_PATTERN_OSNT = 1 };
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
+enum { LBM_BGK = 0, LBM_TRT = 1 };
 /* Solver flag: launch the AA odd step in plain tile order instead of giving
  * each XCD one contiguous range of tiles. */
 enum { LBM_FLAG_NO_XCD_REMAP = 1 };
@@ -81,6 +82,12 @@ typedef struct lbm_lattice lbm_lattice;
  *                >= the largest extent, or 1) means no blocking.
  *                LBM_ORDER_MORTON: Morton space-filling curve (bits of x, y, z
  *                interleaved, x most significant per triple); block ignored.
+ *                LBM_ORDER_HILBERT: Hilbert curve on the bounding 2^b cube
+ *                (the space-filling curve of Sect. 5.6); block ignored.
+ *                LBM_ORDER_HILBERT_LS: two-stage renumbering of Sect. 6.1:
+ *                the Hilbert order is cut into `block` (>= 1) contiguous
+ *                chunks of ceil(N/block) nodes, each re-enumerated by plain
+ *                lexicographic order.
  *
  * Node n is the n-th fluid voxel in that order. For q = 1..18 the adjacency
  * entry of node n is the node at the upstream site x_n - c_q (pull scheme,
@@ -150,7 +157,10 @@ typedef struct lbm_params {
   int64_t lda;       /* adjacency row stride (>= N), adjacency only          */
   int64_t ldr;       /* run_delta row stride (>= R), RIA only                */
   int32_t f16_scale_log2; /* FP16 storage scale exponent s, in [-24, 24]     */
-  int32_t reserved;  /* must be 0                                            */
+  int32_t collision; /* LBM_BGK, or LBM_TRT (two relaxation times, Sect. 2):
+                        f*_q = f_q - w+ (f+_q - feq+_q) - w- (f-_q - feq-_q)
+                        + S_q with w+ = 1/tau and w- fixed by trt_magic      */
+  double trt_magic;  /* TRT: Lambda = (1/w+ - 1/2)(1/w- - 1/2) > 0           */
 } lbm_params;
 
 typedef struct lbm_buffers {

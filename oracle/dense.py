@@ -10,7 +10,8 @@ written on dense arrays ``f[q, x, y, z]`` with one full copy per step.
 The paper names the collision operator (TRT) but gives no formulas, no
 equilibrium, no wall rule and no forcing. The readings used here:
 
-* BGK collision with relaxation time tau (omega = 1/tau);
+* BGK collision with relaxation time tau (omega = 1/tau), or the paper's TRT
+  operator with magic parameter Lambda;
 * second-order equilibrium with c_s^2 = 1/3:
   feq_q = w_q rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u);
 * constant body-force density F added after relaxation as
@@ -82,17 +83,42 @@ def force_source(force):
     return [(3.0 * W[q]) * _cdot(q, force) for q in range(Q)]
 
 
-def collide(f, tau, force):
-    """BGK collision with body force: f*_q = (f_q - omega (f_q - feq_q)) + S_q."""
+def trt_omega_minus(tau, magic):
+    """Relaxation rate of the antisymmetric part for a TRT magic parameter
+    Lambda = (1/omega_plus - 1/2)(1/omega_minus - 1/2)."""
+    return 1.0 / (magic / (tau - 0.5) + 0.5)
+
+
+def collide(f, tau, force, magic=None):
+    """Collision with body force, returns the post-collision PDFs.
+
+    BGK (``magic`` None): f*_q = (f_q - omega (f_q - feq_q)) + S_q.
+    TRT (Sect. 2; two relaxation times, ``magic`` = Lambda): with
+    f+- = (f_q +- f_qbar)/2 and feq+- the symmetric and antisymmetric
+    equilibrium parts, f*_q = ((f_q - w+ (f+ - feq+)) - w- (f- - feq-)) + S_q,
+    w+ = 1/tau, w- from Lambda.
+    """
     omega = 1.0 / tau
     rho, u = macroscopic(f)
     usq = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]
     S = force_source(force)
     out = np.empty_like(f)
+    if magic is None:
+        for q in range(Q):
+            cu = _cdot(q, u)
+            feq = (W[q] * rho) * (((1.0 + 3.0 * cu) + (4.5 * cu) * cu) - 1.5 * usq)
+            out[q] = (f[q] - omega * (f[q] - feq)) + S[q]
+        return out
+    omega_m = trt_omega_minus(tau, magic)
     for q in range(Q):
+        qb = OPP[q]
         cu = _cdot(q, u)
-        feq = (W[q] * rho) * (((1.0 + 3.0 * cu) + (4.5 * cu) * cu) - 1.5 * usq)
-        out[q] = (f[q] - omega * (f[q] - feq)) + S[q]
+        wr = W[q] * rho
+        ep = wr * ((1.0 + (4.5 * cu) * cu) - 1.5 * usq)
+        em = wr * (3.0 * cu)
+        fp = (f[q] + f[qb]) * 0.5
+        fm = (f[q] - f[qb]) * 0.5
+        out[q] = ((f[q] - omega * (fp - ep)) - omega_m * (fm - em)) + S[q]
     return out
 
 
@@ -131,10 +157,10 @@ def stream(fstar, solid, periodic):
     return out
 
 
-def step(f, solid, periodic, tau, force):
+def step(f, solid, periodic, tau, force, magic=None):
     """One time step of eq. (1): collide, then propagate."""
     with np.errstate(all="ignore"):
-        return stream(collide(f, tau, force), solid, periodic)
+        return stream(collide(f, tau, force, magic), solid, periodic)
 
 
 def initial_state(solid, rho=None, u=None):
@@ -150,15 +176,15 @@ def initial_state(solid, rho=None, u=None):
     return f
 
 
-def run(solid, periodic, tau, force, steps, rho=None, u=None, f0=None):
+def run(solid, periodic, tau, force, steps, rho=None, u=None, f0=None, magic=None):
     """Advance f(0) by ``steps`` time steps; returns f(steps) as (19, nx, ny, nz)."""
     f = initial_state(solid, rho, u) if f0 is None else np.array(f0, dtype=np.float64)
     for _ in range(steps):
-        f = step(f, solid, periodic, tau, force)
+        f = step(f, solid, periodic, tau, force, magic)
     return f
 
 
-def cone_sites(solid, periodic, tau, force, steps, rho, u, sites):
+def cone_sites(solid, periodic, tau, force, steps, rho, u, sites, magic=None):
     """PDFs f(steps) at selected fluid sites of a lattice too large to run whole.
 
     After k steps a site depends only on sites within k lattice units
@@ -189,6 +215,6 @@ def cone_sites(solid, periodic, tau, force, steps, rho, u, sites):
             raise ValueError("cone_sites: site %r is solid" % (tuple(s),))
         f = initial_state(crop, rho[ix], [u[a][ix] for a in range(3)])
         for _ in range(int(steps)):
-            f = step(f, crop, (False, False, False), tau, force)
+            f = step(f, crop, (False, False, False), tau, force, magic)
         out[i] = f[:, h, h, h]
     return out

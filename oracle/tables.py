@@ -69,18 +69,69 @@ def morton_keys(vid, shape):
     return key
 
 
+def hilbert_keys(vid, shape):
+    """3-D Hilbert curve index of each voxel (Sect. 5.6 uses a Hilbert curve).
+
+    Skilling's transpose method on the bounding 2^b cube: undo the excess
+    rotations and reflections from the top bit down, Gray-encode, then read
+    the bits of (x, y, z) interleaved, x most significant per triple.
+    """
+    b = max(1, int(np.ceil(np.log2(max(max(shape), 2)))))
+    x, y, z = _coords(vid, shape)
+    X = [x.copy(), y.copy(), z.copy()]
+    Qb = 1 << (b - 1)
+    while Qb > 1:
+        P = Qb - 1
+        for i in range(3):
+            hit = (X[i] & Qb) != 0
+            inv = X[0] ^ P
+            t = (X[0] ^ X[i]) & P
+            X0_new = np.where(hit, inv, X[0] ^ t)
+            if i > 0:
+                X[i] = np.where(hit, X[i], X[i] ^ t)
+            X[0] = X0_new
+        Qb >>= 1
+    for i in range(1, 3):
+        X[i] = X[i] ^ X[i - 1]
+    t = np.zeros_like(X[0])
+    Qb = 1 << (b - 1)
+    while Qb > 1:
+        t = np.where((X[2] & Qb) != 0, t ^ (Qb - 1), t)
+        Qb >>= 1
+    X = [X[i] ^ t for i in range(3)]
+    key = np.zeros(vid.shape, dtype=np.int64)
+    for bit in range(b - 1, -1, -1):
+        for i in range(3):
+            key = (key << 1) | ((X[i] >> bit) & 1)
+    return key
+
+
 def enumerate_nodes(mask, order="lex", block=0):
-    """Fluid-node enumeration: node n sits at voxel ``node_voxel[n]`` (int32)."""
+    """Fluid-node enumeration: node n sits at voxel ``node_voxel[n]`` (int32).
+
+    order: "lex" (LS with blocking factor ``block``), "morton", "hilbert", or
+    "hilbert_ls": the two-stage renumbering of Sect. 6.1 -- the Hilbert order
+    is cut into ``block`` contiguous chunks of ceil(N / block) nodes (the
+    partitions), and every chunk is re-enumerated by plain LS.
+    """
     mask = np.asarray(mask)
     vid = fluid_voxels(mask)
     if order == "lex":
         key = lex_keys(vid, mask.shape, block)
     elif order == "morton":
         key = morton_keys(vid, mask.shape)
+    elif order in ("hilbert", "hilbert_ls"):
+        key = hilbert_keys(vid, mask.shape)
     else:
         raise ValueError(order)
     perm = np.argsort(key, kind="stable")
-    return vid[perm].astype(np.int32)
+    nodes = vid[perm]
+    if order == "hilbert_ls":
+        parts = max(int(block), 1)
+        chunk = -(-len(nodes) // parts) if len(nodes) else 1
+        part = np.arange(len(nodes)) // chunk
+        nodes = nodes[np.lexsort((nodes, part))]
+    return nodes.astype(np.int32)
 
 
 def adjacency(mask, periodic, node_voxel):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_sparse.so")
 
 LBM_OK, LBM_EINVAL, LBM_ERANGE, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
-ORDERS = {"lex": 0, "morton": 1}
+ORDERS = {"lex": 0, "morton": 1, "hilbert": 2, "hilbert_ls": 3}
 PATTERNS = {"aa": 0, "osnt": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2}
 FLAG_NO_XCD_REMAP = 1
@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
         ("lda", ctypes.c_int64),
         ("ldr", ctypes.c_int64),
         ("f16_scale_log2", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
+        ("trt_magic", ctypes.c_double),
     ]
 
 

@@ -39,10 +39,12 @@ constexpr double kW[Q] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 
 
 // Per-launch collision constants (host-computed, passed by value).
 struct Collision {
-  double omega;      // 1 / tau
+  double omega;      // 1 / tau (BGK rate; TRT rate of the symmetric part)
+  double omega_m;    // TRT rate of the antisymmetric part
   double S[Q];       // 3 w_q (c_q . F)
   double rho0;       // reference density of deviation storage
   float omega_f;
+  float omega_m_f;
   float S_f[Q];
   float rho0_f;
   float h_scale[Q];    // FP16 storage: stored value = deviation * h_scale[q]
@@ -118,6 +120,44 @@ __device__ __forceinline__ void collide_f64(double (&f)[Q], const Collision& c) 
   }
 }
 
+// TRT collision (Sect. 2), FP64, in place. With f+- = (f_q +- f_qbar) / 2
+// and the symmetric / antisymmetric equilibrium parts
+// e+ = (w_q rho)((1 + (9/2 cu) cu) - 3/2 u.u), e- = (w_q rho)(3 cu):
+// f*_q = ((f_q - omega (f+ - e+)) - omega_m (f- - e-)) + S_q.
+// Opposite directions are updated as pairs, so no copy of f is kept.
+__device__ __forceinline__ void collide_trt_f64(double (&f)[Q], const Collision& c) {
+  const double rho = density(f);
+  const double jx = momentum<0>(f);
+  const double jy = momentum<1>(f);
+  const double jz = momentum<2>(f);
+  const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+  const double usq = (ux * ux + uy * uy) + uz * uz;
+  {
+    const double wr = kW[0] * rho;
+    const double ep = wr * ((1.0 + (4.5 * 0.0) * 0.0) - 1.5 * usq);
+    const double em = wr * (3.0 * 0.0);
+    const double fp = (f[0] + f[0]) * 0.5, fm = (f[0] - f[0]) * 0.5;
+    f[0] = ((f[0] - c.omega * (fp - ep)) - c.omega_m * (fm - em)) + c.S[0];
+  }
+#pragma unroll
+  for (int q = 1; q < Q; q += 2) {
+    const int b = q + 1;  // kOpp[q]
+    const double cu = cdot<double>(q, ux, uy, uz);
+    const double cub = cdot<double>(b, ux, uy, uz);
+    const double wr = kW[q] * rho;
+    const double ep = wr * ((1.0 + (4.5 * cu) * cu) - 1.5 * usq);
+    const double em = wr * (3.0 * cu);
+    const double epb = wr * ((1.0 + (4.5 * cub) * cub) - 1.5 * usq);
+    const double emb = wr * (3.0 * cub);
+    const double fp = (f[q] + f[b]) * 0.5, fm = (f[q] - f[b]) * 0.5;
+    const double fpb = (f[b] + f[q]) * 0.5, fmb = (f[b] - f[q]) * 0.5;
+    const double nq = ((f[q] - c.omega * (fp - ep)) - c.omega_m * (fm - em)) + c.S[q];
+    const double nb = ((f[b] - c.omega * (fpb - epb)) - c.omega_m * (fmb - emb)) + c.S[b];
+    f[q] = nq;
+    f[b] = nb;
+  }
+}
+
 // ------------------------------------------------------------------------
 // Deviation storage: the grid holds d_q = f_q - w_q rho0 (FP32, or FP16
 // scaled by 2^s / w_q), arithmetic in FP32. Since sum_q w_q = 1 and
@@ -148,6 +188,35 @@ __device__ __forceinline__ void collide_dev_f32(float (&d)[Q], const Collision& 
   }
 }
 
+// TRT on deviations: the rest part w_q rho0 is symmetric, so d- = f- and
+// d+ = f+ - w_q rho0; the equilibrium parts become
+// e+ - w_q rho0 = w_q (drho + rho (9/2 cu^2 - 3/2 u.u)) and e- = w_q rho 3 cu.
+__device__ __forceinline__ void collide_trt_dev_f32(float (&d)[Q], const Collision& c) {
+#pragma clang fp contract(fast)
+  const float drho = density(d);
+  const float rho = c.rho0_f + drho;
+  const float jx = momentum<0>(d);
+  const float jy = momentum<1>(d);
+  const float jz = momentum<2>(d);
+  const float ir = 1.0f / rho;
+  const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+  d[0] = d[0] - c.omega_f * (d[0] - kWf[0] * (drho - rho * usq15)) + c.S_f[0];
+#pragma unroll
+  for (int q = 1; q < Q; q += 2) {
+    const int b = q + 1;
+    const float cu = cdot<float>(q, ux, uy, uz);  // cu of b is -cu
+    const float epd = kWf[q] * (drho + rho * (4.5f * cu * cu - usq15));
+    const float em = kWf[q] * rho * 3.0f * cu;
+    const float dp = 0.5f * (d[q] + d[b]), dm = 0.5f * (d[q] - d[b]);
+    const float sym = c.omega_f * (dp - epd), anti = c.omega_m_f * (dm - em);
+    const float nq = d[q] - sym - anti + c.S_f[q];
+    const float nb = d[b] - sym + anti + c.S_f[b];
+    d[q] = nq;
+    d[b] = nb;
+  }
+}
+
 // Deviation of the equilibrium in FP64 (initialisation of deviation storage).
 __device__ __forceinline__ double equilibrium_dev_f64(int q, double rho, double rho0, double ux,
                                                       double uy, double uz) {
@@ -164,7 +233,13 @@ struct Prec;
 template <>
 struct Prec<double> {
   static constexpr bool kDeviation = false;
-  __device__ static void collide(double (&v)[Q], const Collision& c) { collide_f64(v, c); }
+  template <bool TRT>
+  __device__ static void collide(double (&v)[Q], const Collision& c) {
+    if constexpr (TRT)
+      collide_trt_f64(v, c);
+    else
+      collide_f64(v, c);
+  }
   __device__ static double value64(int, double v, const Collision&) { return v; }
   __device__ static double from64(int, double x, const Collision&) { return x; }
 };
@@ -172,7 +247,13 @@ struct Prec<double> {
 template <>
 struct Prec<float> {
   static constexpr bool kDeviation = true;
-  __device__ static void collide(float (&v)[Q], const Collision& c) { collide_dev_f32(v, c); }
+  template <bool TRT>
+  __device__ static void collide(float (&v)[Q], const Collision& c) {
+    if constexpr (TRT)
+      collide_trt_dev_f32(v, c);
+    else
+      collide_dev_f32(v, c);
+  }
   __device__ static double value64(int, float v, const Collision&) { return (double)v; }
   __device__ static float from64(int, double d, const Collision&) { return (float)d; }
 };
@@ -180,11 +261,15 @@ struct Prec<float> {
 template <>
 struct Prec<_Float16> {
   static constexpr bool kDeviation = true;
+  template <bool TRT>
   __device__ static void collide(_Float16 (&v)[Q], const Collision& c) {
     float d[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) d[q] = (float)v[q] * c.h_unscale[q];
-    collide_dev_f32(d, c);
+    if constexpr (TRT)
+      collide_trt_dev_f32(d, c);
+    else
+      collide_dev_f32(d, c);
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = (_Float16)(d[q] * c.h_scale[q]);
   }

@@ -117,9 +117,11 @@ __device__ __forceinline__ int32_t pull_slot(int q, int32_t n, const int32_t (&a
 
 // ------------------------------------------------------------- step kernels --
 // S is the storage type: double (FP64 arithmetic in the oracle's order),
-// float or _Float16 (deviation storage, FP32 arithmetic).
+// float or _Float16 (deviation storage, FP32 arithmetic). TRT selects the
+// collision (BGK or TRT) at compile time, so each kernel only holds the
+// registers of its own operator.
 
-template <class S>
+template <class S, bool TRT>
 __global__ void __launch_bounds__(kBlock)
 aa_even(S* __restrict__ F, int32_t N, int32_t ldf, Collision c, int remap) {
   const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
@@ -128,12 +130,12 @@ aa_even(S* __restrict__ F, int32_t N, int32_t ldf, Collision c, int remap) {
   S f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = __builtin_nontemporal_load(F + (stream_offset(q, ldf) + n));
-  Prec<S>::collide(f, c);
+  Prec<S>::template collide<TRT>(f, c);
 #pragma unroll
   for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], F + (stream_offset(kOpp[q], ldf) + n));
 }
 
-template <class S, class Idx>
+template <class S, class Idx, bool TRT>
 __global__ void __launch_bounds__(kBlock)
 aa_odd(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, Collision c, int remap) {
   const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
@@ -147,13 +149,13 @@ aa_odd(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, Collision c, int rema
   S f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = F[slot[q]];
-  Prec<S>::collide(f, c);
+  Prec<S>::template collide<TRT>(f, c);
   // f*_q goes where f_qbar came from
 #pragma unroll
   for (int q = 0; q < Q; ++q) F[slot[kOpp[q]]] = f[q];
 }
 
-template <class S, class Idx>
+template <class S, class Idx, bool TRT>
 __global__ void __launch_bounds__(kBlock)
 osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, int32_t ldf, Idx idx, Collision c,
      int remap) {
@@ -168,7 +170,7 @@ osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, int32_t ldf, Idx idx
   S f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = G[slot[q]];
-  Prec<S>::collide(f, c);
+  Prec<S>::template collide<TRT>(f, c);
 #pragma unroll
   for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], H + (stream_offset(q, ldf) + n));
 }

@@ -91,6 +91,36 @@ void radix_sort(std::vector<uint64_t>& key, std::vector<int32_t>& val, int key_b
   }
 }
 
+// Hilbert index of (x, y, z) on the 2^bits cube (Skilling's transpose
+// method): remove the excess rotations / reflections level by level, Gray
+// encode, and read the transposed bits interleaved, x first in each triple.
+uint64_t hilbert_key(uint32_t x, uint32_t y, uint32_t z, int bits) {
+  uint32_t X[3] = {x, y, z};
+  const uint32_t top = 1u << (bits - 1);
+  for (uint32_t Qb = top; Qb > 1; Qb >>= 1) {
+    const uint32_t P = Qb - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Qb) {
+        X[0] ^= P;
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0;
+  for (uint32_t Qb = top; Qb > 1; Qb >>= 1)
+    if (X[2] & Qb) t ^= Qb - 1;
+  for (int i = 0; i < 3; ++i) X[i] ^= t;
+  uint64_t key = 0;
+  for (int b = bits - 1; b >= 0; --b)
+    for (int i = 0; i < 3; ++i) key = (key << 1) | ((X[i] >> b) & 1u);
+  return key;
+}
+
 int enumerate(lbm_lattice* L, const uint8_t* solid, int32_t order, int32_t block) {
   const int64_t nx = L->nx, ny = L->ny, nz = L->nz;
   auto& out = L->node_voxel;
@@ -125,6 +155,27 @@ int enumerate(lbm_lattice* L, const uint8_t* solid, int32_t order, int32_t block
       out.push_back((int32_t)v);
     }
     radix_sort(keys, out, std::max(1, 3 * bits));
+    return LBM_OK;
+  }
+  if (order == LBM_ORDER_HILBERT || order == LBM_ORDER_HILBERT_LS) {
+    if (maxext > (1 << 21)) return fail(LBM_ERANGE, "Hilbert order needs extents <= 2^21");
+    int bits = 1;
+    while ((int64_t(1) << bits) < maxext) ++bits;
+    std::vector<uint64_t> keys;
+    for (int64_t v = 0; v < nx * ny * nz; ++v) {
+      if (solid[v]) continue;
+      keys.push_back(hilbert_key((uint32_t)(v / (ny * nz)), (uint32_t)((v / nz) % ny), (uint32_t)(v % nz), bits));
+      out.push_back((int32_t)v);
+    }
+    radix_sort(keys, out, 3 * bits);
+    if (order == LBM_ORDER_HILBERT_LS) {
+      // two-stage renumbering (Sect. 6.1): partitions are contiguous chunks
+      // of the curve, each re-enumerated lexicographically
+      const int64_t parts = std::max<int32_t>(block, 1);
+      const int64_t n = (int64_t)out.size();
+      const int64_t chunk = n ? (n + parts - 1) / parts : 1;
+      for (int64_t a = 0; a < n; a += chunk) std::sort(out.begin() + a, out.begin() + std::min(n, a + chunk));
+    }
     return LBM_OK;
   }
   return fail(LBM_EINVAL, "unknown order %d", order);

@@ -24,6 +24,7 @@ struct lbm_solver {
   int64_t t = 0;
   int cur = 0;     // OS-NT: grid that holds f*(t-1)
   int remap = 1;   // XCD-aware tile order
+  bool trt = false;
   Collision c;
 };
 
@@ -258,13 +259,8 @@ void dispatch(const lbm_solver* s, void* grid, Fn&& fn) {
   }
 }
 
-int launch_step(lbm_solver* s) {
-  const int32_t N = (int32_t)s->p.n_fluid;
-  if (N == 0) {  // nothing to update; time still advances
-    if (s->p.pattern == LBM_PATTERN_OSNT) s->cur = 1 - s->cur;
-    s->t += 1;
-    return LBM_OK;
-  }
+template <bool TRT>
+void launch_step_op(lbm_solver* s, int32_t N) {
   const unsigned tiles = grid_for(N);
   const unsigned tiles8 = (tiles + 7) / 8 * 8;
   const dim3 b(kBlock);
@@ -273,7 +269,7 @@ int launch_step(lbm_solver* s) {
     if (s->t % 2 == 0) {
       dispatch(s, s->b.pdf[0], [&](auto* F, auto) {
         using S = std::remove_pointer_t<decltype(F)>;
-        hipLaunchKernelGGL(aa_even<S>, dim3(tiles), b, 0, s->stream, F, N, ldf, s->c, 0);
+        hipLaunchKernelGGL((aa_even<S, TRT>), dim3(tiles), b, 0, s->stream, F, N, ldf, s->c, 0);
       });
     } else {
       // the scattered stores of the odd step share partial lines between
@@ -281,7 +277,7 @@ int launch_step(lbm_solver* s) {
       const int remap = s->remap;
       dispatch(s, s->b.pdf[0], [&](auto* F, auto idx) {
         using S = std::remove_pointer_t<decltype(F)>;
-        hipLaunchKernelGGL((aa_odd<S, decltype(idx)>), dim3(remap ? tiles8 : tiles), b, 0, s->stream,
+        hipLaunchKernelGGL((aa_odd<S, decltype(idx), TRT>), dim3(remap ? tiles8 : tiles), b, 0, s->stream,
                            F, N, ldf, idx, s->c, remap);
       });
     }
@@ -290,11 +286,21 @@ int launch_step(lbm_solver* s) {
     void* H = s->b.pdf[1 - s->cur];
     dispatch(s, G, [&](auto* Gt, auto idx) {
       using S = std::remove_pointer_t<decltype(Gt)>;
-      hipLaunchKernelGGL((osnt<S, decltype(idx)>), dim3(tiles), b, 0, s->stream, (const S*)Gt, (S*)H, N,
+      hipLaunchKernelGGL((osnt<S, decltype(idx), TRT>), dim3(tiles), b, 0, s->stream, (const S*)Gt, (S*)H, N,
                          ldf, idx, s->c, 0);
     });
-    s->cur = 1 - s->cur;
   }
+}
+
+int launch_step(lbm_solver* s) {
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N > 0) {
+    if (s->trt)
+      launch_step_op<true>(s, N);
+    else
+      launch_step_op<false>(s, N);
+  }
+  if (s->p.pattern == LBM_PATTERN_OSNT) s->cur = 1 - s->cur;
   s->t += 1;
   return LBM_OK;
 }
@@ -312,7 +318,9 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
     return fail(LBM_EINVAL, "unknown precision %d", p->precision);
   if (p->flags & ~LBM_FLAG_NO_XCD_REMAP) return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
   if (p->f16_scale_log2 < -24 || p->f16_scale_log2 > 24) return fail(LBM_EINVAL, "f16_scale_log2 out of [-24, 24]");
-  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+  if (p->collision != LBM_BGK && p->collision != LBM_TRT) return fail(LBM_EINVAL, "unknown collision %d", p->collision);
+  if (p->collision == LBM_TRT && !(p->trt_magic > 0 && std::isfinite(p->trt_magic)))
+    return fail(LBM_EINVAL, "TRT needs a positive magic parameter");
   if (p->n_fluid < 0) return fail(LBM_EINVAL, "n_fluid < 0");
   if (p->n_fluid > INT32_MAX - 64) return fail(LBM_ERANGE, "n_fluid exceeds the int32 node index");
   if (p->ldf < p->n_fluid || p->ldf % 64 != 0) return fail(LBM_EINVAL, "ldf must be >= N and a multiple of 64");
@@ -366,7 +374,11 @@ int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace
   s->stream = (hipStream_t)hip_stream;
   s->remap = (p->flags & LBM_FLAG_NO_XCD_REMAP) ? 0 : 1;
   Collision& c = s->c;
+  s->trt = p->collision == LBM_TRT;
   c.omega = 1.0 / p->tau;
+  // Lambda = (1/w+ - 1/2)(1/w- - 1/2)  =>  w- = 1 / (Lambda / (tau - 1/2) + 1/2)
+  c.omega_m = s->trt ? 1.0 / (p->trt_magic / (p->tau - 0.5) + 0.5) : c.omega;
+  c.omega_m_f = (float)c.omega_m;
   for (int q = 0; q < Q; ++q) c.S[q] = (3.0 * kW[q]) * cdot<double>(q, p->force[0], p->force[1], p->force[2]);
   c.rho0 = p->rho0;
   c.omega_f = (float)c.omega;

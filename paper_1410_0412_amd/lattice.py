@@ -22,8 +22,10 @@ class Lattice:
 
     mask      uint8 (nx, ny, nz), C order, nonzero = solid.
     periodic  three booleans; outside of a non-periodic axis counts as solid.
-    order     "lex" (lexicographic, x slowest) or "morton".
-    block     LS blocking factor B (0 or 1: none).
+    order     "lex" (lexicographic, x slowest), "morton", "hilbert", or
+              "hilbert_ls" (Hilbert partitions re-enumerated by LS).
+    block     LS blocking factor B (0 or 1: none); for "hilbert_ls" the
+              number of partitions.
     """
 
     def __init__(self, mask, periodic=(True, False, False), order="lex", block=0):

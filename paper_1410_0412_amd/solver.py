@@ -54,11 +54,14 @@ class Solver:
     precision  "f64" (FP64 storage and arithmetic), "f32" or "f16"
                (storage of deviations from the rest state, FP32 arithmetic).
     f16_scale_log2  FP16 storage holds d_q * 2^s / w_q (default s = 10).
+    trt_magic  None: BGK collision; a number Lambda > 0: TRT collision (the
+               paper's operator) with that magic parameter.
     xcd_remap  AA odd step: each XCD sweeps one contiguous tile range.
     """
 
     def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria=True,
-                 precision="f64", rho0=1.0, device=None, xcd_remap=True, f16_scale_log2=10):
+                 precision="f64", rho0=1.0, device=None, xcd_remap=True, f16_scale_log2=10,
+                 trt_magic=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -101,6 +104,8 @@ class Solver:
             p.flags = 0 if xcd_remap else _capi.FLAG_NO_XCD_REMAP
             p.n_fluid, p.n_runs, p.ldf, p.lda, p.ldr = N, R, self.ldf, lda, ldr
             p.f16_scale_log2 = int(f16_scale_log2)
+            p.collision = 0 if trt_magic is None else 1
+            p.trt_magic = 0.0 if trt_magic is None else float(trt_magic)
             self._params = p
             b = _capi.Buffers()
             b.pdf[0] = self.pdf[0].data_ptr()

@@ -46,7 +46,7 @@ def test_spheres32_100_steps(spheres32, pattern, ria):
 
 
 @pytest.mark.parametrize("pattern,ria", VARIANTS)
-@pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 4), ("morton", 0)])
+@pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 4), ("morton", 0), ("hilbert", 0), ("hilbert_ls", 3)])
 def test_every_step_random_state(pattern, ria, order, block):
     # non-trivial seeded initial state; all PDFs compared after every step, so
     # both AA parities and every slot of the layouts are exercised
@@ -131,3 +131,29 @@ def test_errors_from_host():
         Solver(lat, 0.5)
     with pytest.raises(LbmError):
         Solver(lat, float("nan"))
+
+
+@pytest.mark.parametrize("pattern,ria", VARIANTS)
+@pytest.mark.parametrize("magic", [3 / 16, 0.05])
+def test_trt_every_step(pattern, ria, magic):
+    mask = rsa_spheres((18, 16, 20), 2.5, 0.25, PER, seed=15)
+    rho0, u0 = init_fields(mask.shape, seed=16)
+    tau, F = 0.75, (1e-5, 2e-6, -3e-6)
+    lat, s = solver_for(mask, PER, tau, F, pattern, ria, trt_magic=magic)
+    r, v = node_fields(lat, rho0, u0)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    f = dense.initial_state(mask.astype(bool), rho0, u0)
+    for t in range(1, 6):
+        s.step(1)
+        f = dense.step(f, mask.astype(bool), PER, tau, F, magic)
+        assert np.array_equal(s.export_pdfs().cpu().numpy(), oracle_at_nodes(lat, f)), t
+
+
+def test_trt_spheres32_100_steps(spheres32):
+    mask, p, _, _, _ = spheres32
+    f = dense.run(mask.astype(bool), p["periodic"], p["tau"], p["force"], p["steps"], magic=3 / 16)
+    for pattern, ria in VARIANTS:
+        lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], pattern, ria, trt_magic=3 / 16)
+        s.init()
+        s.step(p["steps"])
+        assert np.array_equal(s.export_pdfs().cpu().numpy(), oracle_at_nodes(lat, f))

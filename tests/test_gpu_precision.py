@@ -107,3 +107,19 @@ def test_rest_state_exact():
         s.step(10)
         rho, u, tot = s.moments()
         assert float(u.abs().max()) == 0.0 and float((rho - 1).abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_trt_random_state(prec):
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.25, PER, seed=5)
+    rho0, u0 = init_fields(mask.shape, seed=6)
+    tau, F, magic = 0.65, (2e-5, -1e-5, 5e-6), 3 / 16
+    lat, s = solver_for(mask, PER, tau, F, "aa", True, precision=prec, trt_magic=magic)
+    r, v = node_fields(lat, rho0, u0)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    s.step(40)
+    f = dense.run(mask.astype(bool), PER, tau, F, 40, rho0, u0, magic=magic)
+    e = field_errors(lat, s, f)
+    print("trt random-state %s errors %r" % (prec, e), flush=True)
+    for k, tol in TOL[prec].items():
+        assert e[k] <= tol, (k, e[k])

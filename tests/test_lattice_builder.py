@@ -41,7 +41,8 @@ def test_header_symbols_exported():
         assert hasattr(lib, name), name
 
 
-@pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 1), ("lex", 2), ("lex", 3), ("lex", 5), ("morton", 0)])
+@pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 1), ("lex", 2), ("lex", 3), ("lex", 5), ("morton", 0),
+                                         ("hilbert", 0), ("hilbert_ls", 1), ("hilbert_ls", 3)])
 def test_tiny_masks_all_periodicities(order, block):
     rng = np.random.default_rng(3)
     for shape in [(1, 1, 1), (3, 3, 3), (4, 3, 5), (7, 5, 6), (2, 9, 3)]:
@@ -51,7 +52,8 @@ def test_tiny_masks_all_periodicities(order, block):
                 compare(mask, periodic, order, block)
 
 
-@pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 8), ("lex", 7), ("morton", 0)])
+@pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 8), ("lex", 7), ("morton", 0), ("hilbert", 0),
+                                         ("hilbert_ls", 8)])
 def test_sphere_masks(order, block):
     mask = rsa_spheres((32, 32, 32), 3.0, 0.2, (True, False, False), seed=0)
     compare(mask, (True, False, False), order, block)
@@ -61,7 +63,7 @@ def test_sphere_masks(order, block):
 
 def test_foam_crop():
     mask = foam((48, 40, 36), 3.0, 0.85, seed=2)
-    for order, block in [("lex", 0), ("lex", 8), ("morton", 0)]:
+    for order, block in [("lex", 0), ("lex", 8), ("morton", 0), ("hilbert", 0), ("hilbert_ls", 5)]:
         compare(mask, (True, False, False), order, block)
 
 

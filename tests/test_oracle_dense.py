@@ -149,3 +149,60 @@ def test_cone_sites_match_full_run():
     got = dense.cone_sites(mask, periodic, 0.7, (1e-5, 0, 0), 3, rho0, u0, sites)
     want = np.stack([f[:, s[0], s[1], s[2]] for s in sites])
     assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------------------ TRT ----
+
+def poiseuille_trt(H, tau, F, magic):
+    """Steady TRT plane Poiseuille flow with halfway bounce-back and simple
+    forcing: the wall-location error depends on Lambda only, and u = j/rho
+    without the half-force shift lags the parabola by F/2:
+    u(y) = F/(2 nu) ((y - 1/2)(H + 1/2 - y) + (16 Lambda - 3)/12) - F/2.
+    For BGK (Lambda = (tau - 1/2)^2) this is the closed form above."""
+    y = np.arange(1, H + 1, dtype=float)
+    nu = (tau - 0.5) / 3.0
+    return F / (2 * nu) * ((y - 0.5) * (H + 0.5 - y) + (16 * magic - 3) / 12) - F / 2
+
+
+def test_trt_closed_form_reduces_to_bgk():
+    for tau in (0.6, 0.8, 1.3):
+        np.testing.assert_allclose(poiseuille_trt(8, tau, 1e-5, (tau - 0.5) ** 2),
+                                   poiseuille(8, tau, 1e-5), rtol=1e-12)
+
+
+@pytest.mark.parametrize("tau,magic", [(0.8, 3 / 16), (1.3, 3 / 16), (0.7, 1 / 12), (1.0, 0.25)])
+def test_trt_poiseuille_closed_form(tau, magic):
+    H, F = 8, 1e-5
+    solid = np.zeros((2, H, 2), bool)
+    nu = (tau - 0.5) / 3
+    om = dense.trt_omega_minus(tau, magic)
+    steps = int(40 * H * H / (nu * np.pi ** 2)) + int(200 / min(1 / tau, om))
+    f = dense.run(solid, (True, False, True), tau, (F, 0, 0), steps, magic=magic)
+    rho, u = dense.macroscopic(f)
+    want = poiseuille_trt(H, tau, F, magic)
+    assert np.max(np.abs(u[0][0, :, 0] - want)) / np.max(np.abs(want)) < 1e-10
+
+
+def test_trt_with_bgk_magic_is_bgk():
+    mask = rsa_spheres((10, 10, 10), 2.0, 0.2, (True, False, False), seed=12).astype(bool)
+    rho0, u0 = init_fields(mask.shape, seed=13)
+    tau = 0.8
+    a = dense.run(mask, (True, False, False), tau, (1e-5, 0, 0), 10, rho0, u0)
+    b = dense.run(mask, (True, False, False), tau, (1e-5, 0, 0), 10, rho0, u0, magic=(tau - 0.5) ** 2)
+    np.testing.assert_allclose(b[:, ~mask], a[:, ~mask], rtol=0, atol=1e-15)
+
+
+def test_trt_conservation_and_force():
+    mask = rsa_spheres((14, 12, 10), 2.5, 0.2, (True, False, False), seed=14).astype(bool)
+    rho0, u0 = init_fields(mask.shape, seed=15)
+    f0 = dense.initial_state(mask, rho0, u0)
+    m0 = dense.macroscopic(f0)[0][~mask].sum()
+    f = dense.run(mask, (True, False, False), 0.7, (1e-5, 0, 0), 100, f0=f0, magic=0.1)
+    assert abs(dense.macroscopic(f)[0][~mask].sum() - m0) / m0 < 1e-13
+    shape = (3, 4, 5)
+    solid = np.zeros(shape, bool)
+    g = dense.initial_state(solid)
+    for t in range(1, 11):
+        g = dense.step(g, solid, (True, True, True), 0.9, (2e-5, -1e-5, 3e-6), magic=0.2)
+        _, j = dense.density_and_momentum(g)
+        np.testing.assert_allclose(j[0], t * 2e-5, rtol=1e-11)

@@ -197,3 +197,47 @@ def test_morton_has_no_runs_in_open_box():
     mask = np.zeros((8, 8, 8), np.uint8)
     t = tables.build(mask, (True, True, True), "morton")
     assert len(t["run_start"]) - 1 == 8 * 8 * 8
+
+
+# --------------------------------------------------------------- Hilbert ----
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_hilbert_curve_is_a_face_connected_bijection(k):
+    # the defining property of a Hilbert curve on a 2^k cube: it visits every
+    # cell once and consecutive cells share a face
+    n = 1 << k
+    mask = np.zeros((n, n, n), np.uint8)
+    nodes = tables.enumerate_nodes(mask, "hilbert").astype(np.int64)
+    assert sorted(nodes.tolist()) == list(range(n ** 3))
+    xyz = np.stack([nodes // (n * n), (nodes // n) % n, nodes % n], 1)
+    assert tuple(xyz[0]) == (0, 0, 0)
+    steps = np.abs(np.diff(xyz, axis=0)).sum(1)
+    assert np.all(steps == 1)
+    # the curve of a 2^k cube ends on a corner adjacent to its start corner
+    assert np.count_nonzero(xyz[-1]) == 1 and xyz[-1].max() == n - 1
+
+
+def test_hilbert_sub_box_keeps_curve_order():
+    # a box inside the bounding cube takes the cube's curve order
+    n = 8
+    full = tables.enumerate_nodes(np.zeros((n, n, n), np.uint8), "hilbert").astype(np.int64)
+    mask = np.ones((n, n, n), np.uint8)
+    mask[:5, :6, :7] = 0
+    sub = tables.enumerate_nodes(mask[:5, :6, :7], "hilbert").astype(np.int64)
+    xyz_sub = np.stack([sub // 42, (sub // 7) % 6, sub % 7], 1)
+    xyz_full = [tuple(v) for v in np.stack([full // 64, (full // 8) % 8, full % 8], 1)
+                if v[0] < 5 and v[1] < 6 and v[2] < 7]
+    assert [tuple(v) for v in xyz_sub] == xyz_full
+
+
+def test_hilbert_ls_partitions():
+    mask = (np.random.default_rng(5).random((9, 7, 8)) < 0.3).astype(np.uint8)
+    h = tables.enumerate_nodes(mask, "hilbert")
+    for parts in (1, 3, 4):
+        r = tables.enumerate_nodes(mask, "hilbert_ls", parts)
+        chunk = -(-len(h) // parts)
+        for p in range(parts):
+            a, b = p * chunk, min(len(h), (p + 1) * chunk)
+            # same set of voxels per partition, LS order inside
+            assert sorted(r[a:b].tolist()) == sorted(h[a:b].tolist())
+            assert np.all(np.diff(r[a:b]) > 0)
