@@ -171,6 +171,11 @@ typedef struct lbm_buffers {
   const int32_t* run_delta;   /* device [18][ldr] (ria = 1)                  */
   const uint64_t* head_bits;  /* device [W]       (ria = 1)                  */
   const int32_t* run_base;    /* device [W]       (ria = 1)                  */
+  const double* solid_frac;   /* device [N] partial-bounce-back solid
+                                 fraction ns in [0, 1] per node, or NULL.
+                                 With it every step applies
+                                 post_q = (1 - ns) f*_q + ns f_qbar after the
+                                 BGK collision (AA pattern, FP64, BGK only). */
 } lbm_buffers;
 
 typedef struct lbm_solver lbm_solver;
@@ -224,7 +229,39 @@ int lbm_solver_export_pdfs(lbm_solver* s, double* f);
 /* Set the state to f (device double[19*N], natural order) at time t >= 0. */
 int lbm_solver_import_pdfs(lbm_solver* s, const double* f, int64_t t);
 
+/* Declare that the AA grid currently holds the state of time t (layout by
+ * parity), e.g. after the caller copied a checkpoint into pdf[0].
+ * LBM_ESTATE for OS-NT. */
+int lbm_solver_set_time(lbm_solver* s, int64_t t);
+
+/* out (device double[1]) = sum_n weight[n] * j_axis(n, t) of f(t), FP64,
+ * in a fixed summation order. weight: device double[N]. Synchronises. */
+int lbm_solver_weighted_momentum(lbm_solver* s, const double* weight, int32_t axis, double* out);
+
 void lbm_solver_free(lbm_solver* s);
+
+/* ====================================================================== */
+/* Adjoint of the AA step (AA pattern, FP64, BGK, optional partial         */
+/* bounce-back). Not part of the paper: the differentiation extension.     */
+/* ====================================================================== */
+
+/*
+ * lam (device double[19*ldf], the AA slot layout of time t) = dJ/df(t) for
+ * J = sum_n weight[n] * j_axis(n, t): lam at the slot of f_q(n) is
+ * weight[n] * c_q,axis. Asynchronous.
+ */
+int lbm_adjoint_seed_momentum(lbm_solver* s, const double* weight, int32_t axis, int64_t t,
+                              double* lam);
+
+/*
+ * Backward through the step t -> t+1. fwd: device double[19*ldf], the AA grid
+ * holding f(t) (as the solver held it before stepping from t). lam: on entry
+ * dJ/df(t+1) in the layout of time t+1, on exit dJ/df(t) in the layout of
+ * time t (in place). grad (device double[N] or NULL): dJ/dns(n) accumulates
+ * sum_q mu_q (f_qbar - f*_q), mu_q = dJ/dpost_q. Asynchronous. LBM_ESTATE
+ * unless AA, FP64 and BGK.
+ */
+int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, double* grad);
 
 /* ====================================================================== */
 /* Bandwidth micro-benchmarks (Sect. 5.2, Table 3, GPU analogues)          */

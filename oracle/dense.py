@@ -89,8 +89,11 @@ def trt_omega_minus(tau, magic):
     return 1.0 / (magic / (tau - 0.5) + 0.5)
 
 
-def collide(f, tau, force, magic=None):
+def collide(f, tau, force, magic=None, ns=None):
     """Collision with body force, returns the post-collision PDFs.
+
+    ``ns`` (array of per-site solid fractions in [0, 1], BGK only) applies
+    partial bounce-back: post_q = (1 - ns) f*_q + ns f_qbar.
 
     BGK (``magic`` None): f*_q = (f_q - omega (f_q - feq_q)) + S_q.
     TRT (Sect. 2; two relaxation times, ``magic`` = Lambda): with
@@ -108,7 +111,11 @@ def collide(f, tau, force, magic=None):
             cu = _cdot(q, u)
             feq = (W[q] * rho) * (((1.0 + 3.0 * cu) + (4.5 * cu) * cu) - 1.5 * usq)
             out[q] = (f[q] - omega * (f[q] - feq)) + S[q]
+        if ns is not None:
+            out = np.stack([((1.0 - ns) * out[q]) + (ns * f[OPP[q]]) for q in range(Q)])
         return out
+    if ns is not None:
+        raise ValueError("partial bounce-back is defined for BGK only")
     omega_m = trt_omega_minus(tau, magic)
     for q in range(Q):
         qb = OPP[q]
@@ -157,10 +164,10 @@ def stream(fstar, solid, periodic):
     return out
 
 
-def step(f, solid, periodic, tau, force, magic=None):
+def step(f, solid, periodic, tau, force, magic=None, ns=None):
     """One time step of eq. (1): collide, then propagate."""
     with np.errstate(all="ignore"):
-        return stream(collide(f, tau, force, magic), solid, periodic)
+        return stream(collide(f, tau, force, magic, ns), solid, periodic)
 
 
 def initial_state(solid, rho=None, u=None):
@@ -176,11 +183,11 @@ def initial_state(solid, rho=None, u=None):
     return f
 
 
-def run(solid, periodic, tau, force, steps, rho=None, u=None, f0=None, magic=None):
+def run(solid, periodic, tau, force, steps, rho=None, u=None, f0=None, magic=None, ns=None):
     """Advance f(0) by ``steps`` time steps; returns f(steps) as (19, nx, ny, nz)."""
     f = initial_state(solid, rho, u) if f0 is None else np.array(f0, dtype=np.float64)
     for _ in range(steps):
-        f = step(f, solid, periodic, tau, force, magic)
+        f = step(f, solid, periodic, tau, force, magic, ns)
     return f
 
 

@@ -11,3 +11,4 @@ arguments.
 from ._capi import LbmError, lib  # noqa: F401
 from .lattice import Lattice  # noqa: F401
 from .solver import Solver, bench_stream  # noqa: F401
+from .adjoint import OutletFlux, outlet_flux  # noqa: F401

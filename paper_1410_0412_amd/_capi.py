@@ -58,6 +58,7 @@ class Buffers(ctypes.Structure):
         ("run_delta", ctypes.c_void_p),
         ("head_bits", ctypes.c_void_p),
         ("run_base", ctypes.c_void_p),
+        ("solid_frac", ctypes.c_void_p),
     ]
 
 
@@ -96,6 +97,10 @@ def lib():
         "lbm_solver_import_pdfs": (ctypes.c_int, [vp, vp, ctypes.c_int64]),
         "lbm_solver_free": (None, [vp]),
         "lbm_bench_stream": (ctypes.c_int, [ctypes.c_int32, vp, vp, ctypes.c_int64, ctypes.c_int64, vp]),
+        "lbm_solver_set_time": (ctypes.c_int, [vp, ctypes.c_int64]),
+        "lbm_solver_weighted_momentum": (ctypes.c_int, [vp, vp, ctypes.c_int32, vp]),
+        "lbm_adjoint_seed_momentum": (ctypes.c_int, [vp, vp, ctypes.c_int32, ctypes.c_int64, vp]),
+        "lbm_adjoint_step": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -112,6 +117,7 @@ EXPORTED = [
     "lbm_lattice_free", "lbm_solver_workspace_bytes", "lbm_solver_create", "lbm_solver_set_stream",
     "lbm_solver_init_equilibrium", "lbm_solver_step", "lbm_solver_time", "lbm_solver_moments",
     "lbm_solver_export_pdfs", "lbm_solver_import_pdfs", "lbm_solver_free", "lbm_bench_stream",
+    "lbm_solver_set_time", "lbm_solver_weighted_momentum", "lbm_adjoint_seed_momentum", "lbm_adjoint_step",
 ]
 
 

@@ -1,0 +1,66 @@
+"""Gradient of an outlet momentum flux with respect to per-node
+partial-bounce-back solid fractions, through the hand-written adjoint AA
+kernels (``lbm_adjoint_*``) with checkpointed recomputation.
+
+J(ns) = sum_n weight[n] * j_axis(n, T) after T AA steps from the rest state.
+The forward pass stores the AA grid every ``every`` steps. The backward pass
+walks the segments from last to first: it restores a checkpoint, recomputes
+the segment storing each grid, and runs the adjoint step over those grids in
+reverse. Device memory: ceil(T / every) + every grids.
+"""
+
+from __future__ import annotations
+
+import torch
+
+
+class OutletFlux(torch.autograd.Function):
+    """``OutletFlux.apply(ns, solver, steps, every, weight, axis)`` -> J (0-dim).
+
+    ``solver`` must be an AA / FP64 / BGK :class:`Solver` created with
+    ``pbb=True``; ``ns`` and ``weight`` are device float64 tensors of shape
+    (N,) in node order.
+    """
+
+    @staticmethod
+    def forward(ctx, ns, solver, steps, every, weight, axis=0):
+        steps, every = int(steps), int(every)
+        if steps < 0 or every < 1:
+            raise ValueError("steps >= 0 and every >= 1 required")
+        solver.set_solid_fraction(ns.detach())
+        solver.init()
+        ckpts = []
+        for t in range(steps):
+            if t % every == 0:
+                ckpts.append((t, solver.pdf[0].clone()))
+            solver.step(1)
+        J = solver.weighted_momentum(weight, axis)
+        ctx.solver, ctx.steps, ctx.every, ctx.axis = solver, steps, every, axis
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(weight)
+        return J
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (weight,) = ctx.saved_tensors
+        s, T, every = ctx.solver, ctx.steps, ctx.every
+        lam = torch.empty_like(s.pdf[0])
+        grad = torch.zeros(s.n_fluid, dtype=torch.float64, device=s.device)
+        s.adjoint_seed(weight, ctx.axis, T, lam)
+        for t0, ck in reversed(ctx.ckpts):
+            t1 = min(t0 + every, T)
+            s.pdf[0].copy_(ck)
+            s.set_time(t0)
+            states = []
+            for _ in range(t0, t1):
+                states.append(s.pdf[0].clone())
+                s.step(1)
+            for t in range(t1 - 1, t0 - 1, -1):
+                s.adjoint_step(states[t - t0], t, lam, grad)
+        ctx.ckpts = None
+        return grad * gJ, None, None, None, None, None
+
+
+def outlet_flux(ns, solver, steps, every, weight, axis=0):
+    """J(ns) as a differentiable function of ``ns`` (see :class:`OutletFlux`)."""
+    return OutletFlux.apply(ns, solver, steps, every, weight, axis)

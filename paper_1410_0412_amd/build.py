@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm_sparse.so")
 
 SOURCES = ["lattice.cpp", "solver.hip"]
-HEADERS = ["common.hpp", "d3q19.hpp", "kernels.hpp"]
+HEADERS = ["common.hpp", "d3q19.hpp", "kernels.hpp", "adjoint.hpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-pthread",

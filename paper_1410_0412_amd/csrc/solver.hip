@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace lbm;
@@ -153,6 +154,34 @@ moments(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Co
   if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Partial sums of w_n j_axis(n) of f(t) (FP64).
+template <class S, class Idx>
+__global__ void __launch_bounds__(kBlock)
+weighted_momentum(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Collision c,
+                  const double* __restrict__ w, int axis, double* __restrict__ partial) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x; n64 < N;
+       n64 += (int64_t)gridDim.x * kBlock) {
+    const int32_t n = (int32_t)n64;
+    int32_t s[Q];
+    state_slots(layout, n, idx, ldf, s);
+    double f[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = Prec<S>::value64(q, F[s[q]], c);
+    const double j = axis == 0 ? momentum<0>(f) : (axis == 1 ? momentum<1>(f) : momentum<2>(f));
+    acc = acc + w[n] * j;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = kBlock / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + k];
+    __syncthreads();
+  }
+  // same partial layout as the moments kernel: 4 doubles per block
+  if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = threadIdx.x == 0 ? red[0] : 0.0;
+}
+
 __global__ void __launch_bounds__(kBlock)
 finish_totals(const double* __restrict__ partial, int nparts, double* __restrict__ totals) {
   __shared__ double red[4][kBlock];
@@ -292,9 +321,29 @@ void launch_step_op(lbm_solver* s, int32_t N) {
   }
 }
 
+void launch_step_pbb(lbm_solver* s, int32_t N) {
+  double* F = (double*)s->b.pdf[0];
+  const int32_t ldf = (int32_t)s->p.ldf;
+  auto go = [&](auto idx) {
+    using I = decltype(idx);
+    if (s->t % 2 == 0)
+      hipLaunchKernelGGL((aa_step_pbb<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N, ldf,
+                         idx, s->c, s->b.solid_frac);
+    else
+      hipLaunchKernelGGL((aa_step_pbb<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N, ldf,
+                         idx, s->c, s->b.solid_frac);
+  };
+  if (s->p.ria)
+    go(index_ria(s));
+  else
+    go(index_ia(s));
+}
+
 int launch_step(lbm_solver* s) {
   const int32_t N = (int32_t)s->p.n_fluid;
-  if (N > 0) {
+  if (N > 0 && s->b.solid_frac) {
+    launch_step_pbb(s, N);
+  } else if (N > 0) {
     if (s->trt)
       launch_step_op<true>(s, N);
     else
@@ -327,6 +376,8 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
   if (p->ldf > (int64_t)INT32_MAX / Q) return fail(LBM_ERANGE, "19 * ldf exceeds the int32 slot index");
   if (!b->pdf[0]) return fail(LBM_EINVAL, "pdf[0] is null");
   if (p->pattern == LBM_PATTERN_OSNT && !b->pdf[1]) return fail(LBM_EINVAL, "OS-NT needs pdf[1]");
+  if (b->solid_frac && (p->pattern != LBM_PATTERN_AA || p->precision != LBM_F64 || p->collision != LBM_BGK))
+    return fail(LBM_EINVAL, "partial bounce-back needs the AA pattern, FP64 and BGK");
   if (p->ria) {
     if (p->n_runs < 0 || (p->n_fluid > 0 && p->n_runs < 1)) return fail(LBM_EINVAL, "n_runs invalid");
     if (p->ldr < p->n_runs) return fail(LBM_EINVAL, "ldr < n_runs");
@@ -350,7 +401,7 @@ const char* lbm_last_error(void) { return error_buffer(); }
 int lbm_solver_workspace_bytes(const lbm_params* p, int64_t* bytes) {
   clear_error();
   if (!p || !bytes) return fail(LBM_EINVAL, "null pointer");
-  *bytes = (int64_t)kRedBlocks * 4 * sizeof(double);
+  *bytes = ((int64_t)kRedBlocks * 4 + 4) * sizeof(double);
   return LBM_OK;
 }
 
@@ -488,6 +539,95 @@ int lbm_solver_import_pdfs(lbm_solver* s, const double* f, int64_t t) {
                        N, (int32_t)s->p.ldf, idx, layout, s->c, f);
   });
   return device_status("import_pdfs");
+}
+
+int lbm_solver_set_time(lbm_solver* s, int64_t t) {
+  clear_error();
+  if (!s) return fail(LBM_EINVAL, "null solver");
+  if (t < 0) return fail(LBM_EINVAL, "t < 0");
+  if (s->p.pattern != LBM_PATTERN_AA) return fail(LBM_ESTATE, "set_time is defined for the AA pattern");
+  s->t = t;
+  return LBM_OK;
+}
+
+int lbm_solver_weighted_momentum(lbm_solver* s, const double* weight, int32_t axis, double* out) {
+  clear_error();
+  if (!s || !weight || !out) return fail(LBM_EINVAL, "null pointer");
+  if (axis < 0 || axis > 2) return fail(LBM_EINVAL, "axis must be 0, 1 or 2");
+  const int32_t N = (int32_t)s->p.n_fluid;
+  unsigned parts = 0;
+  if (N > 0) {
+    parts = std::min<unsigned>(grid_for(N), kRedBlocks);
+    const int layout = current_layout(s);
+    dispatch(s, current_grid(s), [&](auto* F, auto idx) {
+      using S = std::remove_pointer_t<decltype(F)>;
+      hipLaunchKernelGGL((weighted_momentum<S, decltype(idx)>), dim3(parts), dim3(kBlock), 0, s->stream,
+                         (const S*)F, N, (int32_t)s->p.ldf, idx, layout, s->c, weight, (int)axis, s->ws);
+    });
+  }
+  hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, s->ws, (int)parts, s->ws + 4 * kRedBlocks);
+  if (hipMemcpyAsync(out, s->ws + 4 * kRedBlocks, sizeof(double), hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
+    return device_status("weighted_momentum (copy)");
+  int rc = device_status("weighted_momentum");
+  if (rc) return rc;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return device_status("weighted_momentum (sync)");
+  return LBM_OK;
+}
+
+namespace {
+int adjoint_ready(const lbm_solver* s) {
+  if (s->p.pattern != LBM_PATTERN_AA || s->p.precision != LBM_F64 || s->trt)
+    return fail(LBM_ESTATE, "the adjoint is defined for AA, FP64, BGK");
+  return LBM_OK;
+}
+}  // namespace
+
+int lbm_adjoint_seed_momentum(lbm_solver* s, const double* weight, int32_t axis, int64_t t, double* lam) {
+  clear_error();
+  if (!s || !weight || !lam) return fail(LBM_EINVAL, "null pointer");
+  if (axis < 0 || axis > 2 || t < 0) return fail(LBM_EINVAL, "bad axis or time");
+  int rc = adjoint_ready(s);
+  if (rc) return rc;
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N == 0) return LBM_OK;
+  auto go = [&](auto idx) {
+    using I = decltype(idx);
+    if (t % 2 == 0)
+      hipLaunchKernelGGL((adjoint_seed<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, lam, N,
+                         (int32_t)s->p.ldf, idx, weight, (int)axis);
+    else
+      hipLaunchKernelGGL((adjoint_seed<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, lam, N,
+                         (int32_t)s->p.ldf, idx, weight, (int)axis);
+  };
+  if (s->p.ria)
+    go(index_ria(s));
+  else
+    go(index_ia(s));
+  return device_status("adjoint_seed_momentum");
+}
+
+int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, double* grad) {
+  clear_error();
+  if (!s || !fwd || !lam) return fail(LBM_EINVAL, "null pointer");
+  if (t < 0) return fail(LBM_EINVAL, "t < 0");
+  int rc = adjoint_ready(s);
+  if (rc) return rc;
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N == 0) return LBM_OK;
+  auto go = [&](auto idx) {
+    using I = decltype(idx);
+    if (t % 2 == 0)
+      hipLaunchKernelGGL((aa_adjoint<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, fwd, lam, N,
+                         (int32_t)s->p.ldf, idx, s->c, s->b.solid_frac, grad);
+    else
+      hipLaunchKernelGGL((aa_adjoint<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, fwd, lam, N,
+                         (int32_t)s->p.ldf, idx, s->c, s->b.solid_frac, grad);
+  };
+  if (s->p.ria)
+    go(index_ria(s));
+  else
+    go(index_ia(s));
+  return device_status("adjoint_step");
 }
 
 void lbm_solver_free(lbm_solver* s) { delete s; }

@@ -56,12 +56,14 @@ class Solver:
     f16_scale_log2  FP16 storage holds d_q * 2^s / w_q (default s = 10).
     trt_magic  None: BGK collision; a number Lambda > 0: TRT collision (the
                paper's operator) with that magic parameter.
+    pbb        True: allocate a per-node partial-bounce-back solid fraction
+               (``solid_frac``, zero-initialised; AA, FP64, BGK only).
     xcd_remap  AA odd step: each XCD sweeps one contiguous tile range.
     """
 
     def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria=True,
                  precision="f64", rho0=1.0, device=None, xcd_remap=True, f16_scale_log2=10,
-                 trt_magic=None):
+                 trt_magic=None, pbb=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -83,6 +85,7 @@ class Solver:
         with torch.cuda.device(dev):
             self.pdf = [aligned_empty(torch, 19 * self.ldf, dtype, dev) for _ in range(ngrids)]
             self.adj = self.run_delta = self.head_bits = self.run_base = None
+            self.solid_frac = torch.zeros(max(N, 1), dtype=torch.float64, device=dev) if pbb else None
             lda = ldr = 0
             if self.ria:
                 ldr = _round_up(max(R, 1), 64)
@@ -114,6 +117,7 @@ class Solver:
             b.run_delta = self.run_delta.data_ptr() if self.ria else None
             b.head_bits = self.head_bits.data_ptr() if self.ria else None
             b.run_base = self.run_base.data_ptr() if self.ria else None
+            b.solid_frac = self.solid_frac.data_ptr() if pbb else None
             self._buffers = b
             L = _capi.lib()
             nbytes = ctypes.c_int64()
@@ -182,6 +186,31 @@ class Solver:
         f = self.torch.empty((19, self.n_fluid), dtype=self.torch.float64, device=self.device)
         self._call(_capi.lib().lbm_solver_export_pdfs, _vp(f))
         return f
+
+    def set_time(self, t):
+        """Declare that ``pdf[0]`` holds the AA state of time ``t``."""
+        self._call(_capi.lib().lbm_solver_set_time, int(t))
+
+    def set_solid_fraction(self, ns):
+        """Copy per-node solid fractions (N,) into the partial-bounce-back buffer."""
+        if self.solid_frac is None:
+            raise RuntimeError("solver was created without pbb=True")
+        self.solid_frac[: self.n_fluid].copy_(self._dev(ns, (self.n_fluid,)))
+
+    def weighted_momentum(self, weight, axis=0):
+        """sum_n weight[n] j_axis(n, t) of f(t), FP64 (0-dim tensor)."""
+        w = self._dev(weight, (self.n_fluid,))
+        out = self.torch.empty((), dtype=self.torch.float64, device=self.device)
+        self._call(_capi.lib().lbm_solver_weighted_momentum, _vp(w), int(axis), _vp(out))
+        return out
+
+    def adjoint_seed(self, weight, axis, t, lam):
+        w = self._dev(weight, (self.n_fluid,))
+        self._call(_capi.lib().lbm_adjoint_seed_momentum, _vp(w), int(axis), int(t), _vp(lam))
+        self._keep = (w,)
+
+    def adjoint_step(self, fwd, t, lam, grad):
+        self._call(_capi.lib().lbm_adjoint_step, _vp(fwd), int(t), _vp(lam), _vp(grad))
 
     def import_pdfs(self, f, t=0):
         g = self._dev(f, (19, self.n_fluid))
