@@ -69,9 +69,60 @@ def measured_traffic(kernel, workload):
     except (OSError, ValueError):
         return None
     e = doc.get("kernels", {}).get(kernel)
-    if not e or e.get("workload") != workload or doc.get("source_digest") != source_digest():
+    if not e or doc.get("workload") != workload or doc.get("source_digest") != source_digest():
         return None
     return e.get("hbm_bytes_per_launch")
+
+
+def kernel_key(name):
+    """Short kernel name of a demangled rocprofv3 kernel name."""
+    name = name.replace("(anonymous namespace)::", "").replace("lbm::", "").replace("void ", "")
+    depth, out = 0, []
+    for ch in name:
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def traffic_from(fetch_csv, write_csv, workload_name, command):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch). Both counters are scaled by what they read
+    for the copy micro-benchmark, whose bytes are known."""
+    import csv
+
+    def load(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = kernel_key(r["Kernel_Name"])
+            acc.setdefault(k, []).append(float(r["Counter_Value"]) * 1024.0)
+        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    mask, p = __import__("lbm_inputs").workload(workload_name)
+    n = int((mask == 0).sum())
+    ld = (n + 63) // 64 * 64
+    copy_bytes = 8 * 19 * ld  # read once and written once by the copy kernel
+    sf = copy_bytes / fetch["bench_copy"][0]
+    sw = copy_bytes / write["bench_copy"][0]
+    kernels = {}
+    for k in sorted(set(fetch) & set(write)):
+        if k.startswith("bench_") or k.startswith("at::"):
+            continue
+        fb, wb = fetch[k][0] * sf, write[k][0] * sw
+        kernels[k] = {"fetch_bytes": int(fb), "write_bytes": int(wb), "hbm_bytes_per_launch": int(fb + wb),
+                      "dispatches": fetch[k][1]}
+    doc = {"workload": workload_name, "source_digest": source_digest(),
+           "scale": {"fetch": round(sf, 4), "write": round(sw, 4),
+                     "reference": "copy micro-benchmark of %d bytes" % copy_bytes},
+           "command": command, "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(doc, fh, indent=1)
+    return doc
 
 
 def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup):
@@ -140,6 +191,81 @@ def cpu_baseline(mask, p, steps=2):
                       % (steps, WORKLOAD, solid.size, n)}
 
 
+def order_sweep(torch, args):
+    """Sect. 5.6 analogue: AA-RIA throughput and run density per enumeration."""
+    from lbm_inputs import workload
+    from paper_1410_0412_amd import Lattice
+
+    log("generating", args.workload)
+    mask, p = workload(args.workload, seed=args.seed)
+    out = {"metric": METRIC + " (enumeration sweep)", "unit": "MFLUP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "data": "synthetic",
+           "config": {"workload": args.workload, "porosity": round(float(1 - mask.mean()), 5), "tau": p["tau"]},
+           "orders": {}}
+    for spec in args.orders.split(","):
+        order, _, blk = spec.partition(":")
+        blk = int(blk or 0)
+        t0 = time.perf_counter()
+        lat = Lattice(mask, p["periodic"], order, blk)
+        tb = time.perf_counter() - t0
+        N, R, W = lat.n_fluid, lat.n_runs, lat.n_waves
+        row = {"fluid_nodes": N, "runs_per_node": round(R / N, 5), "lattice_build_s": round(tb, 2)}
+        for prec in ("f64", "f32"):
+            wall, d_e, d_o = time_variant(torch, lat, p, "aa", True, prec, args.steps, args.warmup)
+            sb = 8 if prec == "f64" else 4
+            mflups = 2 * N * args.steps / wall / 1e6
+            bl = (kernel_bytes("even", N, R, W, sb) + kernel_bytes("odd_ria", N, R, W, sb)) / 2 / N
+            row[prec] = {"mflups": round(mflups, 1), "even_us": round(float(np.mean(d_e)) * 1e6, 1),
+                         "odd_us": round(float(np.mean(d_o)) * 1e6, 1), "loop_balance_B_per_FLUP": round(bl, 2),
+                         "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4)}
+        log(spec, row)
+        out["orders"][spec] = row
+        del lat
+    print(json.dumps(out), flush=True)
+
+
+def precision_study(torch, args):
+    """FP32 / FP16 deviation storage against the FP64 path on one workload."""
+    from lbm_inputs import workload
+    from paper_1410_0412_amd import Lattice, Solver
+
+    log("generating", args.workload)
+    mask, p = workload(args.workload, seed=args.seed)
+    lat = Lattice(mask, p["periodic"], p["order"], p["block"])
+    steps = args.steps
+    res, ref = {}, None
+    for prec in ("f64", "f32", "f16"):
+        s = Solver(lat, p["tau"], p["force"], pattern="aa", ria=True, precision=prec)
+        s.init()
+        _, _, t0 = s.moments()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for k in range(0, steps, 1000):
+            s.step(min(1000, steps - k))
+            torch.cuda.synchronize()
+            log(prec, "step", min(k + 1000, steps))
+        wall = time.perf_counter() - w0
+        rho, u, t1 = s.moments()
+        row = {"mflups": round(lat.n_fluid * steps / wall / 1e6, 1),
+               "mass_drift_rel": abs(t1[0].item() - t0[0].item()) / t0[0].item()}
+        if ref is None:
+            ref = (rho, u)
+        else:
+            du = torch.sqrt(((u - ref[1]) ** 2).sum(0)).max() / torch.sqrt((ref[1] ** 2).sum(0)).max()
+            row.update({"u_normwise_rel_err_vs_f64": du.item(),
+                        "rho_max_abs_err_vs_f64": (rho - ref[0]).abs().max().item(),
+                        "ux_max_rel_err_vs_f64": ((u[0] - ref[1][0]).abs().max() / ref[1][0].abs().max()).item()})
+        row["u_max"] = u.abs().max().item()
+        res[prec] = row
+        log(prec, row)
+        del s
+    out = {"metric": "error of deviation storage vs the FP64 GPU path", "n_gpus": 1, "steps": steps,
+           "data": "synthetic", "config": {"workload": args.workload, "fluid_nodes": lat.n_fluid,
+                                           "variant": "AA-RIA", "tau": p["tau"], "force": list(p["force"])},
+           "precisions": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,7 +274,20 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="named synthetic workload (default: the 512x128x128 sphere pack)")
+    ap.add_argument("--orders", default=None,
+                    help="enumeration sweep instead of the default line, e.g. lex:0,lex:8,morton,hilbert")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
+    ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="FP32/FP16 deviation storage vs FP64 after --steps time steps on --workload")
     args = ap.parse_args()
+    if args.traffic_from:
+        doc = traffic_from(args.traffic_from[0], args.traffic_from[1], args.workload, args.traffic_command)
+        print(json.dumps(doc["kernels"], indent=1))
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -162,6 +301,13 @@ def main():
     from lbm_inputs import workload
     from paper_1410_0412_amd import Lattice
 
+    if args.orders:
+        return order_sweep(torch, args)
+    if args.precision_study:
+        return precision_study(torch, args)
+    if args.workload != WORKLOAD:
+        print("the default line is defined on %s; use --orders for other workloads" % WORKLOAD, file=sys.stderr)
+        sys.exit(2)
     log("generating", WORKLOAD)
     mask, p = workload(WORKLOAD, seed=args.seed)
     t0 = time.perf_counter()
@@ -209,7 +355,7 @@ def main():
     odd_bytes = kernel_bytes("odd_ria", N, R, W)
     odd_s = float(np.mean(main_odd))
     achieved = odd_bytes / odd_s / 1e9
-    traffic = measured_traffic("aa_odd_f64<IndexRIA>", WORKLOAD)
+    traffic = measured_traffic("aa_odd<double, IndexRIA, false>", WORKLOAD)
     out = {
         "metric": METRIC,
         "value": aa["mflups"],
@@ -235,7 +381,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "aa_odd_f64<IndexRIA>",
+            "kernel": "aa_odd<double, IndexRIA, false>",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
