@@ -396,6 +396,10 @@ def main():
             "frac": aa["frac_of_hbm_roofline"],
             "paper_model_B_l_aa_r": round(304 + 38 * r, 3),
         },
+        "fp32": {"value": res["aa_ria_f32"]["mflups"], "unit": "MFLUP/s",
+                 "frac_of_hbm_roofline": res["aa_ria_f32"]["frac_of_hbm_roofline"],
+                 "loop_balance_B_per_FLUP": res["aa_ria_f32"]["loop_balance_B_per_FLUP"],
+                 "storage": "d_q = f_q - w_q rho0 in FP32, FP32 arithmetic"},
         "variants": res,
         "microbench_GBs": micro,
     }

@@ -63,3 +63,27 @@ def test_spherepack_variants_identical_and_conserve_mass(pack):
         del s
     for r in results[1:]:
         assert np.array_equal(r, results[0])
+
+
+@pytest.mark.parametrize("order,block", [("lex", 0), ("morton", 0), ("hilbert_ls", 8)])
+def test_foam384_sampled_sites(order, block):
+    # the 384^3 foam of the enumeration sweep and the precision study
+    mask, p = workload("foam-384", seed=0)
+    steps = 2
+    rho0, u0 = init_fields(mask.shape, seed=21)
+    fl = np.flatnonzero(mask.reshape(-1) == 0)
+    pick = fl[np.random.default_rng(22).choice(len(fl), 24, replace=False)]
+    sites = np.stack(np.unravel_index(pick, mask.shape), 1)
+    want = dense.cone_sites(mask.astype(bool), p["periodic"], p["tau"], p["force"], steps, rho0, u0, sites)
+    print("case foam-384 sampled", order, block, flush=True)
+    lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], "aa", True, order, block)
+    r, v = node_fields(lat, rho0, u0)
+    del rho0, u0
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    s.step(steps)
+    f = s.export_pdfs()
+    node_of = np.full(mask.size, -1, np.int64)
+    node_of[lat.node_voxel().astype(np.int64)] = np.arange(lat.n_fluid)
+    idx = torch.from_numpy(node_of[pick]).cuda()
+    got = f[:, idx].T.cpu().numpy()
+    assert np.array_equal(got, want)
