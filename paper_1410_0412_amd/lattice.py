@@ -42,6 +42,7 @@ class Lattice:
         _capi.check(L.lbm_lattice_build(_ptr(m), *self.shape, pmask, _capi.ORDERS[order],
                                         self.block, ctypes.byref(h)))
         self._h = h
+        self._free = L.lbm_lattice_free  # bound now: module globals may be gone at exit
         n, r, w = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _capi.check(L.lbm_lattice_sizes(h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(w)))
         self.n_fluid, self.n_runs, self.n_waves = n.value, r.value, w.value
@@ -49,7 +50,7 @@ class Lattice:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _capi.lib().lbm_lattice_free(h)
+            self._free(h)
             self._h = None
 
     def node_voxel(self):

@@ -128,6 +128,7 @@ class Solver:
                                             _vp(self.workspace), self.workspace.numel(),
                                             ctypes.c_void_p(self._stream()), ctypes.byref(h)))
             self._h = h
+            self._free = L.lbm_solver_free  # bound now: module globals may be gone at exit
 
     # ------------------------------------------------------------------
     def _stream(self):
@@ -142,7 +143,7 @@ class Solver:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _capi.lib().lbm_solver_free(h)
+            self._free(h)
             self._h = None
 
     # ------------------------------------------------------------------
