@@ -1,0 +1,110 @@
+"""Argument validation of the solver C ABI, on the CPU: lbm_solver_create
+checks its parameters before it touches the device, so invalid calls can be
+exercised with placeholder pointers that are never dereferenced."""
+import ctypes
+
+import pytest
+
+capi = pytest.importorskip("paper_1410_0412_amd._capi")
+L = capi.lib()
+
+DUMMY = 0x1000  # never dereferenced: every case below fails validation or creates no work
+
+
+def params(**kw):
+    p = capi.Params()
+    p.tau, p.rho0 = 0.8, 1.0
+    p.pattern, p.ria, p.precision, p.flags = 0, 0, 0, 0
+    p.n_fluid, p.n_runs, p.ldf, p.lda, p.ldr = 100, 10, 128, 128, 64
+    p.f16_scale_log2, p.collision, p.trt_magic = 10, 0, 0.0
+    for k, v in kw.items():
+        if k == "force":
+            for a in range(3):
+                p.force[a] = v[a]
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def buffers(**kw):
+    b = capi.Buffers()
+    b.pdf[0] = DUMMY
+    b.pdf[1] = DUMMY
+    b.adj = b.run_delta = b.head_bits = b.run_base = DUMMY
+    b.solid_frac = None
+    for k, v in kw.items():
+        setattr(b, k, v)
+    return b
+
+
+def create(p, b, ws_bytes=None):
+    need = ctypes.c_int64()
+    assert L.lbm_solver_workspace_bytes(ctypes.byref(p), ctypes.byref(need)) == 0
+    h = ctypes.c_void_p()
+    rc = L.lbm_solver_create(ctypes.byref(p), ctypes.byref(b), ctypes.c_void_p(DUMMY),
+                             need.value if ws_bytes is None else ws_bytes, None, ctypes.byref(h))
+    if rc == 0:
+        L.lbm_solver_free(h)
+    return rc
+
+
+def test_valid_parameters_create():
+    assert create(params(), buffers()) == 0
+    assert create(params(ria=1), buffers()) == 0
+    assert create(params(pattern=1, precision=2, collision=1, trt_magic=0.1875), buffers()) == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(tau=0.5), capi.LBM_EINVAL),
+    (dict(tau=float("nan")), capi.LBM_EINVAL),
+    (dict(force=(float("inf"), 0, 0)), capi.LBM_EINVAL),
+    (dict(rho0=0.0), capi.LBM_EINVAL),
+    (dict(pattern=2), capi.LBM_EINVAL),
+    (dict(ria=2), capi.LBM_EINVAL),
+    (dict(precision=3), capi.LBM_EINVAL),
+    (dict(flags=2), capi.LBM_EINVAL),
+    (dict(collision=1, trt_magic=0.0), capi.LBM_EINVAL),
+    (dict(collision=2), capi.LBM_EINVAL),
+    (dict(f16_scale_log2=30), capi.LBM_EINVAL),
+    (dict(ldf=100), capi.LBM_EINVAL),            # not a multiple of 64
+    (dict(ldf=64), capi.LBM_EINVAL),             # < N
+    (dict(lda=50), capi.LBM_EINVAL),
+    (dict(n_fluid=2 ** 31), capi.LBM_ERANGE),
+    (dict(n_fluid=120_000_000, ldf=120_000_000, lda=120_000_000), capi.LBM_ERANGE),  # 19 * ldf > 2^31 - 1
+    (dict(ria=1, ldr=5), capi.LBM_EINVAL),
+    (dict(ria=1, n_runs=0), capi.LBM_EINVAL),
+])
+def test_invalid_parameters(kw, code):
+    assert create(params(**kw), buffers()) == code
+    assert L.lbm_last_error()
+
+
+def test_missing_buffers_and_workspace():
+    assert create(params(), buffers(adj=None)) == capi.LBM_EINVAL
+    assert create(params(ria=1), buffers(run_delta=None)) == capi.LBM_EINVAL
+    assert create(params(pattern=1), buffers(pdf=(ctypes.c_void_p * 2)(DUMMY, None))) == capi.LBM_EINVAL
+    assert create(params(), buffers(), ws_bytes=8) == capi.LBM_EINVAL
+
+
+def test_partial_bounce_back_restrictions():
+    assert create(params(), buffers(solid_frac=DUMMY)) == 0
+    assert create(params(pattern=1), buffers(solid_frac=DUMMY)) == capi.LBM_EINVAL
+    assert create(params(precision=1), buffers(solid_frac=DUMMY)) == capi.LBM_EINVAL
+    assert create(params(collision=1, trt_magic=0.2), buffers(solid_frac=DUMMY)) == capi.LBM_EINVAL
+
+
+def test_bench_stream_validation():
+    vp = ctypes.c_void_p
+    assert L.lbm_bench_stream(9, vp(DUMMY), vp(DUMMY), 10, 10, None) == capi.LBM_EINVAL
+    assert L.lbm_bench_stream(0, vp(DUMMY), vp(DUMMY), -1, 0, None) == capi.LBM_EINVAL
+    assert L.lbm_bench_stream(1, vp(DUMMY), vp(DUMMY), 10, 5, None) == capi.LBM_EINVAL
+    assert L.lbm_bench_stream(0, vp(DUMMY + 8), vp(DUMMY), 10, 0, None) == capi.LBM_EINVAL
+    assert L.lbm_bench_stream(0, vp(DUMMY), vp(DUMMY), 0, 0, None) == 0  # nothing to do
+
+
+def test_null_handles():
+    t = ctypes.c_int64()
+    assert L.lbm_solver_step(None, 1) == capi.LBM_EINVAL
+    assert L.lbm_solver_time(None, ctypes.byref(t)) == capi.LBM_EINVAL
+    assert L.lbm_solver_moments(None, None, None, None) == capi.LBM_EINVAL
+    assert L.lbm_lattice_sizes(None, None, None, None) == capi.LBM_EINVAL
