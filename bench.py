@@ -125,10 +125,10 @@ def traffic_from(fetch_csv, write_csv, workload_name, command):
     return doc
 
 
-def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup):
+def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_remap=True):
     from paper_1410_0412_amd import Solver
 
-    s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=precision)
+    s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=precision, xcd_remap=xcd_remap)
     s.init()
     s.step(2 * warmup)
     torch.cuda.synchronize()
@@ -266,6 +266,39 @@ def precision_study(torch, args):
     print(json.dumps(out), flush=True)
 
 
+def stride_sweep(torch, args):
+    """U-19A (19-stream in-place update, the AA even-step traffic) for stream
+    strides padded by different amounts: the effect of the paper's padding
+    (Sect. 4.3) on the GPU."""
+    from paper_1410_0412_amd import bench_stream
+
+    n = 3336242
+    base = (n + 63) // 64 * 64
+    mib2 = (2 << 20) // 8
+    strides = [base + k * 64 for k in (0, 1, 2, 3, 5, 8, 16, 32, 64, 128, 256, 1024)]
+    strides += [(n + mib2 - 1) // mib2 * mib2]
+    out = {"metric": "U-19A GB/s vs stream stride (2 * 19 * 8 B per node)", "n_gpus": 1, "nodes": n, "rows": []}
+    cap = 19 * (max(strides) + mib2)
+    buf = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    off = (-buf.data_ptr() % (2 << 20)) // 8
+    a = buf[off:]
+    for ld in strides:
+        for _ in range(3):
+            bench_stream(2, a, a, n, ld)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(30):
+            bench_stream(2, a, a, n, ld)
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = 2 * 8 * 19 * n * 30 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        row = {"stride": ld, "pad_elems": ld - base, "stride_bytes_mod_2MiB": (ld * 8) % (2 << 20), "GBs": round(gbs, 1)}
+        out["rows"].append(row)
+        log(row)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +314,8 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
+    ap.add_argument("--stride-sweep", action="store_true",
+                    help="U-19A bandwidth against the padding of the stream stride")
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32/FP16 deviation storage vs FP64 after --steps time steps on --workload")
     args = ap.parse_args()
@@ -305,6 +340,8 @@ def main():
         return order_sweep(torch, args)
     if args.precision_study:
         return precision_study(torch, args)
+    if args.stride_sweep:
+        return stride_sweep(torch, args)
     if args.workload != WORKLOAD:
         print("the default line is defined on %s; use --orders for other workloads" % WORKLOAD, file=sys.stderr)
         sys.exit(2)
@@ -317,15 +354,15 @@ def main():
     r = R / N
     log("lattice N=%d R=%d r=%.4f built in %.2fs" % (N, R, r, t_build))
 
-    variants = [("aa", True, "f64"), ("aa", True, "f32")]
+    variants = [("aa", True, "f64", True), ("aa", True, "f32", True)]
     if not args.no_variants:
-        variants += [("aa", False, "f64"), ("osnt", False, "f64"), ("osnt", True, "f64"),
-                     ("aa", True, "f16")]
+        variants += [("aa", False, "f64", True), ("osnt", False, "f64", True), ("osnt", True, "f64", True),
+                     ("aa", True, "f16", True), ("aa", True, "f64", False)]
     res = {}
-    for pattern, ria, prec in variants:
-        key = "%s_%s_%s" % (pattern, "ria" if ria else "ia", prec)
+    for pattern, ria, prec, remap in variants:
+        key = "%s_%s_%s%s" % (pattern, "ria" if ria else "ia", prec, "" if remap else "_no_xcd_remap")
         log("timing", key)
-        wall, d_a, d_b = time_variant(torch, lat, p, pattern, ria, prec, args.steps, args.warmup)
+        wall, d_a, d_b = time_variant(torch, lat, p, pattern, ria, prec, args.steps, args.warmup, remap)
         mflups = 2 * N * args.steps / wall / 1e6
         sb = {"f64": 8, "f32": 4, "f16": 2}[prec]
         if pattern == "aa":
