@@ -387,6 +387,11 @@ def main():
 
     micro = microbench(torch, N)
     log("micro-benchmarks GB/s", micro)
+    # Sect. 5.2: the Roofline with the access-pattern-matched micro-benchmark
+    # (U-19A for the AA pattern, CNT-19A for OS-NT) as the bandwidth
+    for key, row in res.items():
+        bw = micro["U-19A" if key.startswith("aa") else "CNT-19A"]
+        row["frac_of_matched_roofline"] = round(row["mflups"] / (bw * 1e3 / row["loop_balance_B_per_FLUP"]), 4)
 
     aa = res["aa_ria_f64"]
     odd_bytes = kernel_bytes("odd_ria", N, R, W)
@@ -431,6 +436,9 @@ def main():
             "loop_balance_B_per_FLUP": aa["loop_balance_B_per_FLUP"],
             "roofline_mflups_at_8TBs": round(HBM_PEAK_GBS * 1e3 / aa["loop_balance_B_per_FLUP"], 1),
             "frac": aa["frac_of_hbm_roofline"],
+            "matched_bandwidth_GBs": micro["U-19A"],
+            "matched_roofline_mflups": round(micro["U-19A"] * 1e3 / aa["loop_balance_B_per_FLUP"], 1),
+            "frac_of_matched_roofline": aa["frac_of_matched_roofline"],
             "paper_model_B_l_aa_r": round(304 + 38 * r, 3),
         },
         "fp32": {"value": res["aa_ria_f32"]["mflups"], "unit": "MFLUP/s",
