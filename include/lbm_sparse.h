@@ -152,8 +152,10 @@ typedef struct lbm_params {
   int32_t flags;     /* LBM_FLAG_NO_XCD_REMAP, or 0                          */
   int64_t n_fluid;   /* N                                                    */
   int64_t n_runs;    /* R (RIA only)                                         */
-  int64_t ldf;       /* elements between direction streams, >= N, multiple
-                        of 64, 19*ldf <= 2^31 - 1                            */
+  int64_t ldf;       /* node slots of the grid: >= N, a multiple of 64,
+                        19*ldf <= 2^31 - 1. Grid layout (tile-major SoA):
+                        direction q of node n = 64t + l is element
+                        (19t + q)*64 + l; a grid holds 19*ldf elements.     */
   int64_t lda;       /* adjacency row stride (>= N), adjacency only          */
   int64_t ldr;       /* run_delta row stride (>= R), RIA only                */
   int32_t f16_scale_log2; /* FP16 storage scale exponent s, in [-24, 24]     */
@@ -166,7 +168,8 @@ typedef struct lbm_params {
 typedef struct lbm_buffers {
   void* pdf[2];               /* device PDF grids, 19*ldf elements of the
                                  storage type (double, float or IEEE half)
-                                 each; pdf[1] only for OS-NT                 */
+                                 each, tile-major (see ldf); pdf[1] only for
+                                 OS-NT                                       */
   const int32_t* adj;         /* device [18][lda] (ria = 0)                  */
   const int32_t* run_delta;   /* device [18][ldr] (ria = 1)                  */
   const uint64_t* head_bits;  /* device [W]       (ria = 1)                  */
@@ -246,7 +249,7 @@ void lbm_solver_free(lbm_solver* s);
 /* ====================================================================== */
 
 /*
- * lam (device double[19*ldf], the AA slot layout of time t) = dJ/df(t) for
+ * lam (device double[19*ldf], the tile-major AA slot layout of time t) = dJ/df(t) for
  * J = sum_n weight[n] * j_axis(n, t): lam at the slot of f_q(n) is
  * weight[n] * c_q,axis. Asynchronous.
  */
@@ -275,6 +278,11 @@ int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, d
  *        (the traffic pattern of the AA even step); src unused.
  * kind 3 "U-1A": one stream of n doubles updated in place in dst; src unused.
  * kind 4 "CNT-1A": copy of one stream of n doubles (same as kind 0).
+ * kind 5 "U-19T": the U-19A update in the tile-major layout of the PDF grid
+ *        (19 rows of 64 doubles per 64-node tile, in place in dst; needs
+ *        ld >= n rounded up to 64, dst of 19*ld doubles); src unused.
+ * kind 6 "CNT-19T": the CNT-19A copy in the tile-major layout, src -> dst
+ *        (both 19*ld doubles, ld >= n rounded up to 64).
  * Asynchronous on hip_stream.
  */
 int lbm_bench_stream(int32_t kind, const double* src, double* dst, int64_t n, int64_t ld,

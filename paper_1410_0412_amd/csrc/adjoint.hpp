@@ -7,7 +7,7 @@
 //
 // Adjoint of one AA step. A step gathers f_q from slot G_q(n) and scatters
 // post_q to slot G_qbar(n): G_q(n) = (q, n) in even steps and L_q(n) in odd
-// steps. The adjoint grid Lam uses the same slot layout. Its step gathers
+// steps. The adjoint grid Lam uses the same (tile-major) slot layout. Its step gathers
 // mu_q = Lam[G_qbar(n)] = dJ/dpost_q and scatters lam_k = dJ/df_k to
 // G_k(n). Each node touches the same slot set as in the forward step, so the
 // adjoint also runs in place without races, backwards in time.
@@ -24,27 +24,27 @@
 namespace lbm {
 
 template <class Idx, bool ODD>
-__device__ __forceinline__ void step_slots(int32_t n, const Idx& idx, int32_t ldf, int32_t (&g)[Q]) {
+__device__ __forceinline__ void step_slots(int32_t n, const Idx& idx, int32_t (&g)[Q]) {
   if constexpr (ODD) {
     int32_t a[18];
     idx.get(n, a);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = aa_slot(q, n, a, ldf);
+    for (int q = 0; q < Q; ++q) g[q] = aa_slot(q, n, a);
   } else {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = stream_offset(q, ldf) + n;
+    for (int q = 0; q < Q; ++q) g[q] = pdf_slot(q, n);
   }
 }
 
 template <class Idx, bool ODD>
 __global__ void __launch_bounds__(kBlock)
-aa_step_pbb(double* __restrict__ F, int32_t N, int32_t ldf, Idx idx, Collision c,
+aa_step_pbb(double* __restrict__ F, int32_t N, Idx idx, Collision c,
             const double* __restrict__ ns) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t g[Q];
-  step_slots<Idx, ODD>(n, idx, ldf, g);
+  step_slots<Idx, ODD>(n, idx, g);
   double f[Q], fs[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = fs[q] = F[g[q]];
@@ -56,13 +56,13 @@ aa_step_pbb(double* __restrict__ F, int32_t N, int32_t ldf, Idx idx, Collision c
 
 template <class Idx, bool ODD>
 __global__ void __launch_bounds__(kBlock)
-aa_adjoint(const double* __restrict__ F, double* __restrict__ Lam, int32_t N, int32_t ldf, Idx idx,
+aa_adjoint(const double* __restrict__ F, double* __restrict__ Lam, int32_t N, Idx idx,
            Collision c, const double* __restrict__ ns, double* __restrict__ grad) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t g[Q];
-  step_slots<Idx, ODD>(n, idx, ldf, g);
+  step_slots<Idx, ODD>(n, idx, g);
   double f[Q], mu[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = F[g[q]];
@@ -98,13 +98,13 @@ aa_adjoint(const double* __restrict__ F, double* __restrict__ Lam, int32_t N, in
 // Lam = dJ/df(t) for J = sum_n w_n j_axis(n, t), in the slot layout of time t.
 template <class Idx, bool ODD>
 __global__ void __launch_bounds__(kBlock)
-adjoint_seed(double* __restrict__ Lam, int32_t N, int32_t ldf, Idx idx, const double* __restrict__ w,
+adjoint_seed(double* __restrict__ Lam, int32_t N, Idx idx, const double* __restrict__ w,
              int axis) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t g[Q];
-  step_slots<Idx, ODD>(n, idx, ldf, g);
+  step_slots<Idx, ODD>(n, idx, g);
   const double wn = w[n];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {

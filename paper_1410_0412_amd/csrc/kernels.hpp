@@ -1,11 +1,12 @@
 // Propagation-step kernels for gfx950 (one lane per fluid node).
 //
-// PDF storage: F[q*ldf + n], 19 direction streams of one element per fluid
-// node (structure of arrays), ldf a multiple of 64 so that every stream of a
-// 64-node wavefront tile starts on its own aligned segment. A wavefront of 64
-// consecutive nodes therefore loads and stores each direction as one
-// contiguous 64-element segment whenever the nodes lie in one run, which is
-// what reduced indirect addressing exploits.
+// PDF storage, tile-major structure of arrays: node n = 64 t + l keeps its
+// direction q at element (19 t + q) * 64 + l. A 64-node wavefront tile thus
+// loads and stores each direction as one coalesced 64-element segment, and
+// the 19 segments of a tile are adjacent: a wave streams one contiguous
+// block instead of 19 distant streams (the 19 "arrays" of Sect. 4.3 become
+// 19 rows of one tile). Neighbour gathers of the odd step stay contiguous
+// inside runs, which is what reduced indirect addressing exploits.
 //
 // Propagation patterns (Sect. 4):
 //  * AA, even step (direct): read (q, n), collide, write f*_q to (qbar, n).
@@ -88,31 +89,33 @@ struct IndexRIA {
 };
 
 // Slots are 32-bit element offsets into the grid (the host guarantees
-// 19 * ldf < 2^31). Stream offsets q * ldf are wave-uniform and kept in
-// scalar registers; per lane a slot costs one compare, two selects and one
-// add, with no branch.
-__device__ __forceinline__ int32_t stream_offset(int q, int32_t ldf) {
-  return __builtin_amdgcn_readfirstlane(q * ldf);
+// 19 * ldf < 2^31 elements). Per lane a slot costs a compare, two selects
+// and a few integer operations, with no branch.
+constexpr int32_t kTile = 64;
+
+// Offset of direction 0 of node m; direction q lies q * 64 elements further.
+__device__ __forceinline__ int32_t node_base(int32_t m) {
+  return (m & ~(kTile - 1)) * Q + (m & (kTile - 1));
 }
 
-__device__ __forceinline__ int32_t select_slot(int32_t an, int32_t n, int32_t base_fluid,
-                                               int32_t base_wall) {
+__device__ __forceinline__ int32_t pdf_slot(int q, int32_t m) { return node_base(m) + q * kTile; }
+
+// AA odd-step slot of f_q for node n: L_q(n) = (qbar at a_q(n)) or (q at n).
+__device__ __forceinline__ int32_t aa_slot(int q, int32_t n, const int32_t (&a)[18]) {
+  if (q == 0) return node_base(n);
+  const int32_t an = a[q - 1];
   const bool fluid = an >= 0;
-  const int32_t idx = fluid ? an : n;
-  const int32_t base = fluid ? base_fluid : base_wall;
-  return base + idx;
+  const int32_t m = fluid ? an : n;
+  return node_base(m) + (fluid ? kOpp[q] : q) * kTile;
 }
 
-// AA odd-step slot of f_q for node n: L_q(n).
-__device__ __forceinline__ int32_t aa_slot(int q, int32_t n, const int32_t (&a)[18], int32_t ldf) {
-  if (q == 0) return n;
-  return select_slot(a[q - 1], n, stream_offset(kOpp[q], ldf), stream_offset(q, ldf));
-}
-
-// OS-NT pull slot of f_q for node n.
-__device__ __forceinline__ int32_t pull_slot(int q, int32_t n, const int32_t (&a)[18], int32_t ldf) {
-  if (q == 0) return n;
-  return select_slot(a[q - 1], n, stream_offset(q, ldf), stream_offset(kOpp[q], ldf));
+// OS-NT pull slot of f_q for node n: (q at a_q(n)) or (qbar at n).
+__device__ __forceinline__ int32_t pull_slot(int q, int32_t n, const int32_t (&a)[18]) {
+  if (q == 0) return node_base(n);
+  const int32_t an = a[q - 1];
+  const bool fluid = an >= 0;
+  const int32_t m = fluid ? an : n;
+  return node_base(m) + (fluid ? q : kOpp[q]) * kTile;
 }
 
 // ------------------------------------------------------------- step kernels --
@@ -123,21 +126,22 @@ __device__ __forceinline__ int32_t pull_slot(int q, int32_t n, const int32_t (&a
 
 template <class S, bool TRT>
 __global__ void __launch_bounds__(kBlock)
-aa_even(S* __restrict__ F, int32_t N, int32_t ldf, Collision c, int remap) {
+aa_even(S* __restrict__ F, int32_t N, Collision c, int remap) {
   const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
+  S* Fn = F + node_base(n);
   S f[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = __builtin_nontemporal_load(F + (stream_offset(q, ldf) + n));
+  for (int q = 0; q < Q; ++q) f[q] = __builtin_nontemporal_load(Fn + q * kTile);
   Prec<S>::template collide<TRT>(f, c);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], F + (stream_offset(kOpp[q], ldf) + n));
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], Fn + kOpp[q] * kTile);
 }
 
 template <class S, class Idx, bool TRT>
 __global__ void __launch_bounds__(kBlock)
-aa_odd(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, Collision c, int remap) {
+aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int remap) {
   const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
@@ -145,7 +149,7 @@ aa_odd(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, Collision c, int rema
   idx.get(n, a);
   int32_t slot[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) slot[q] = aa_slot(q, n, a, ldf);
+  for (int q = 0; q < Q; ++q) slot[q] = aa_slot(q, n, a);
   S f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = F[slot[q]];
@@ -157,8 +161,7 @@ aa_odd(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, Collision c, int rema
 
 template <class S, class Idx, bool TRT>
 __global__ void __launch_bounds__(kBlock)
-osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, int32_t ldf, Idx idx, Collision c,
-     int remap) {
+osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, Idx idx, Collision c, int remap) {
   const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
@@ -166,13 +169,14 @@ osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, int32_t ldf, Idx idx
   idx.get(n, a);
   int32_t slot[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) slot[q] = pull_slot(q, n, a, ldf);
+  for (int q = 0; q < Q; ++q) slot[q] = pull_slot(q, n, a);
   S f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = G[slot[q]];
   Prec<S>::template collide<TRT>(f, c);
+  S* Hn = H + node_base(n);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], H + (stream_offset(q, ldf) + n));
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], Hn + q * kTile);
 }
 
 }  // namespace lbm

@@ -38,27 +38,26 @@ constexpr int kRedBlocks = 1024;  // fixed grid of the reduction: deterministic 
 enum Layout : int { kNatural = 0, kAAOdd = 1, kPull = 2 };
 
 template <class Idx>
-__device__ __forceinline__ void state_slots(int layout, int32_t n, const Idx& idx, int32_t ldf,
-                                            int32_t (&s)[Q]) {
+__device__ __forceinline__ void state_slots(int layout, int32_t n, const Idx& idx, int32_t (&s)[Q]) {
   if (layout == kNatural) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] = q * ldf + n;
+    for (int q = 0; q < Q; ++q) s[q] = pdf_slot(q, n);
     return;
   }
   int32_t a[18];
   idx.get(n, a);
   if (layout == kAAOdd) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] = aa_slot(q, n, a, ldf);
+    for (int q = 0; q < Q; ++q) s[q] = aa_slot(q, n, a);
   } else {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] = pull_slot(q, n, a, ldf);
+    for (int q = 0; q < Q; ++q) s[q] = pull_slot(q, n, a);
   }
 }
 
 template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-init_eq(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout,
+init_eq(S* __restrict__ F, int32_t N, Idx idx, int layout,
         const double* __restrict__ rho, const double* __restrict__ u, Collision c) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
@@ -73,7 +72,7 @@ init_eq(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout,
     equilibrium_f64(r, ux, uy, uz, v);
   }
   int32_t s[Q];
-  state_slots(layout, n, idx, ldf, s);
+  state_slots(layout, n, idx, s);
 #pragma unroll
   for (int q = 0; q < Q; ++q) F[s[q]] = Prec<S>::from64(q, v[q], c);
 }
@@ -81,13 +80,13 @@ init_eq(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout,
 // f(t) in natural order, FP64.
 template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-gather_pdfs(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Collision c,
+gather_pdfs(const S* __restrict__ F, int32_t N, Idx idx, int layout, Collision c,
             double* __restrict__ out) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t s[Q];
-  state_slots(layout, n, idx, ldf, s);
+  state_slots(layout, n, idx, s);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const double v = Prec<S>::value64(q, F[s[q]], c);
@@ -97,13 +96,13 @@ gather_pdfs(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout
 
 template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-scatter_pdfs(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Collision c,
+scatter_pdfs(S* __restrict__ F, int32_t N, Idx idx, int layout, Collision c,
              const double* __restrict__ in) {
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t s[Q];
-  state_slots(layout, n, idx, ldf, s);
+  state_slots(layout, n, idx, s);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const double f = in[(int64_t)q * N + n];
@@ -116,7 +115,7 @@ scatter_pdfs(S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Col
 // over the deviations, rho = rho0 + sum_q d_q.
 template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-moments(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Collision c,
+moments(const S* __restrict__ F, int32_t N, Idx idx, int layout, Collision c,
         double* __restrict__ rho_out, double* __restrict__ u_out, double* __restrict__ partial) {
   __shared__ double red[4][kBlock];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -124,7 +123,7 @@ moments(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Co
        n64 += (int64_t)gridDim.x * kBlock) {
     const int32_t n = (int32_t)n64;
     int32_t s[Q];
-    state_slots(layout, n, idx, ldf, s);
+    state_slots(layout, n, idx, s);
     double f[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) f[q] = Prec<S>::value64(q, F[s[q]], c);
@@ -157,7 +156,7 @@ moments(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Co
 // Partial sums of w_n j_axis(n) of f(t) (FP64).
 template <class S, class Idx>
 __global__ void __launch_bounds__(kBlock)
-weighted_momentum(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int layout, Collision c,
+weighted_momentum(const S* __restrict__ F, int32_t N, Idx idx, int layout, Collision c,
                   const double* __restrict__ w, int axis, double* __restrict__ partial) {
   __shared__ double red[kBlock];
   double acc = 0.0;
@@ -165,7 +164,7 @@ weighted_momentum(const S* __restrict__ F, int32_t N, int32_t ldf, Idx idx, int 
        n64 += (int64_t)gridDim.x * kBlock) {
     const int32_t n = (int32_t)n64;
     int32_t s[Q];
-    state_slots(layout, n, idx, ldf, s);
+    state_slots(layout, n, idx, s);
     double f[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) f[q] = Prec<S>::value64(q, F[s[q]], c);
@@ -241,6 +240,31 @@ bench_u19(double* __restrict__ F, int64_t n, int64_t ld, double s) {
   for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q] * s, F + q * ld + i);
 }
 
+// The same update in the tile-major layout of the PDF grid.
+__global__ void __launch_bounds__(kBlock)
+bench_u19_tiles(double* __restrict__ F, int64_t n, double s) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double* Fi = F + (i & ~(int64_t)(kTile - 1)) * Q + (i & (kTile - 1));
+  double v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = __builtin_nontemporal_load(Fi + q * kTile);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q] * s, Fi + q * kTile);
+}
+
+__global__ void __launch_bounds__(kBlock)
+bench_cnt19_tiles(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = (i & ~(int64_t)(kTile - 1)) * Q + (i & (kTile - 1));
+  double v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = __builtin_nontemporal_load(src + o + q * kTile);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q], dst + o + q * kTile);
+}
+
 __global__ void __launch_bounds__(kBlock)
 bench_u1(double* __restrict__ F, int64_t n, double s) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -293,12 +317,11 @@ void launch_step_op(lbm_solver* s, int32_t N) {
   const unsigned tiles = grid_for(N);
   const unsigned tiles8 = (tiles + 7) / 8 * 8;
   const dim3 b(kBlock);
-  const int32_t ldf = (int32_t)s->p.ldf;
   if (s->p.pattern == LBM_PATTERN_AA) {
     if (s->t % 2 == 0) {
       dispatch(s, s->b.pdf[0], [&](auto* F, auto) {
         using S = std::remove_pointer_t<decltype(F)>;
-        hipLaunchKernelGGL((aa_even<S, TRT>), dim3(tiles), b, 0, s->stream, F, N, ldf, s->c, 0);
+        hipLaunchKernelGGL((aa_even<S, TRT>), dim3(tiles), b, 0, s->stream, F, N, s->c, 0);
       });
     } else {
       // the scattered stores of the odd step share partial lines between
@@ -307,7 +330,7 @@ void launch_step_op(lbm_solver* s, int32_t N) {
       dispatch(s, s->b.pdf[0], [&](auto* F, auto idx) {
         using S = std::remove_pointer_t<decltype(F)>;
         hipLaunchKernelGGL((aa_odd<S, decltype(idx), TRT>), dim3(remap ? tiles8 : tiles), b, 0, s->stream,
-                           F, N, ldf, idx, s->c, remap);
+                           F, N, idx, s->c, remap);
       });
     }
   } else {
@@ -316,21 +339,20 @@ void launch_step_op(lbm_solver* s, int32_t N) {
     dispatch(s, G, [&](auto* Gt, auto idx) {
       using S = std::remove_pointer_t<decltype(Gt)>;
       hipLaunchKernelGGL((osnt<S, decltype(idx), TRT>), dim3(tiles), b, 0, s->stream, (const S*)Gt, (S*)H, N,
-                         ldf, idx, s->c, 0);
+                         idx, s->c, 0);
     });
   }
 }
 
 void launch_step_pbb(lbm_solver* s, int32_t N) {
   double* F = (double*)s->b.pdf[0];
-  const int32_t ldf = (int32_t)s->p.ldf;
   auto go = [&](auto idx) {
     using I = decltype(idx);
     if (s->t % 2 == 0)
-      hipLaunchKernelGGL((aa_step_pbb<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N, ldf,
+      hipLaunchKernelGGL((aa_step_pbb<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N,
                          idx, s->c, s->b.solid_frac);
     else
-      hipLaunchKernelGGL((aa_step_pbb<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N, ldf,
+      hipLaunchKernelGGL((aa_step_pbb<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N,
                          idx, s->c, s->b.solid_frac);
   };
   if (s->p.ria)
@@ -464,7 +486,7 @@ int lbm_solver_init_equilibrium(lbm_solver* s, const double* rho, const double* 
   dispatch(s, s->b.pdf[0], [&](auto* F, auto idx) {
     using S = std::remove_pointer_t<decltype(F)>;
     hipLaunchKernelGGL((init_eq<S, decltype(idx)>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N,
-                       (int32_t)s->p.ldf, idx, layout, rho, u, s->c);
+                       idx, layout, rho, u, s->c);
   });
   return device_status("init_equilibrium");
 }
@@ -495,7 +517,7 @@ int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals) {
     dispatch(s, current_grid(s), [&](auto* F, auto idx) {
       using S = std::remove_pointer_t<decltype(F)>;
       hipLaunchKernelGGL((moments<S, decltype(idx)>), dim3(parts), dim3(kBlock), 0, s->stream, (const S*)F,
-                         N, (int32_t)s->p.ldf, idx, layout, s->c, rho, u, s->ws);
+                         N, idx, layout, s->c, rho, u, s->ws);
     });
   }
   if (totals)  // with no partials the finishing kernel writes zeros
@@ -515,7 +537,7 @@ int lbm_solver_export_pdfs(lbm_solver* s, double* f) {
     dispatch(s, current_grid(s), [&](auto* F, auto idx) {
       using S = std::remove_pointer_t<decltype(F)>;
       hipLaunchKernelGGL((gather_pdfs<S, decltype(idx)>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream,
-                         (const S*)F, N, (int32_t)s->p.ldf, idx, layout, s->c, f);
+                         (const S*)F, N, idx, layout, s->c, f);
     });
   }
   int rc = device_status("export_pdfs");
@@ -536,7 +558,7 @@ int lbm_solver_import_pdfs(lbm_solver* s, const double* f, int64_t t) {
   dispatch(s, current_grid(s), [&](auto* F, auto idx) {
     using S = std::remove_pointer_t<decltype(F)>;
     hipLaunchKernelGGL((scatter_pdfs<S, decltype(idx)>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F,
-                       N, (int32_t)s->p.ldf, idx, layout, s->c, f);
+                       N, idx, layout, s->c, f);
   });
   return device_status("import_pdfs");
 }
@@ -562,7 +584,7 @@ int lbm_solver_weighted_momentum(lbm_solver* s, const double* weight, int32_t ax
     dispatch(s, current_grid(s), [&](auto* F, auto idx) {
       using S = std::remove_pointer_t<decltype(F)>;
       hipLaunchKernelGGL((weighted_momentum<S, decltype(idx)>), dim3(parts), dim3(kBlock), 0, s->stream,
-                         (const S*)F, N, (int32_t)s->p.ldf, idx, layout, s->c, weight, (int)axis, s->ws);
+                         (const S*)F, N, idx, layout, s->c, weight, (int)axis, s->ws);
     });
   }
   hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, s->ws, (int)parts, s->ws + 4 * kRedBlocks);
@@ -594,10 +616,10 @@ int lbm_adjoint_seed_momentum(lbm_solver* s, const double* weight, int32_t axis,
     using I = decltype(idx);
     if (t % 2 == 0)
       hipLaunchKernelGGL((adjoint_seed<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, lam, N,
-                         (int32_t)s->p.ldf, idx, weight, (int)axis);
+                         idx, weight, (int)axis);
     else
       hipLaunchKernelGGL((adjoint_seed<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, lam, N,
-                         (int32_t)s->p.ldf, idx, weight, (int)axis);
+                         idx, weight, (int)axis);
   };
   if (s->p.ria)
     go(index_ria(s));
@@ -618,10 +640,10 @@ int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, d
     using I = decltype(idx);
     if (t % 2 == 0)
       hipLaunchKernelGGL((aa_adjoint<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, fwd, lam, N,
-                         (int32_t)s->p.ldf, idx, s->c, s->b.solid_frac, grad);
+                         idx, s->c, s->b.solid_frac, grad);
     else
       hipLaunchKernelGGL((aa_adjoint<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, fwd, lam, N,
-                         (int32_t)s->p.ldf, idx, s->c, s->b.solid_frac, grad);
+                         idx, s->c, s->b.solid_frac, grad);
   };
   if (s->p.ria)
     go(index_ria(s));
@@ -656,6 +678,15 @@ int lbm_bench_stream(int32_t kind, const double* src, double* dst, int64_t n, in
     case 2:
       if (!dst || ld < n) return fail(LBM_EINVAL, "U-19A needs dst and ld >= n");
       hipLaunchKernelGGL(bench_u19, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, n, ld, 1.0);
+      break;
+    case 5:
+      if (!dst || ld < (n + kTile - 1) / kTile * kTile) return fail(LBM_EINVAL, "U-19T needs dst and ld >= n rounded to 64");
+      hipLaunchKernelGGL(bench_u19_tiles, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, n, 1.0);
+      break;
+    case 6:
+      if (!src || !dst || ld < (n + kTile - 1) / kTile * kTile)
+        return fail(LBM_EINVAL, "CNT-19T needs src, dst and ld >= n rounded to 64");
+      hipLaunchKernelGGL(bench_cnt19_tiles, dim3(grid_for(n)), dim3(kBlock), 0, st, src, dst, n);
       break;
     case 3:
       if (!dst) return fail(LBM_EINVAL, "U-1A needs dst");

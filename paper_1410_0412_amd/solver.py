@@ -22,22 +22,15 @@ def _vp(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-_STREAM_ALIGN = 2 << 20  # bytes
+_GRID_ALIGN = 2 << 20  # bytes
 
 
-def grid_stride(n, elem_bytes):
-    """Elements between direction streams: >= n, a multiple of 64, and for
-    large grids a multiple of 2 MiB, so every stream starts on a 2 MiB
-    boundary (the GPU counterpart of the paper's padding against cache and
-    TLB thrashing, Sect. 4.3)."""
-    ld = _round_up(max(n, 1), 64)
-    big = _round_up(ld, _STREAM_ALIGN // elem_bytes)
-    if 8 * (big - ld) <= ld and 19 * big <= 2 ** 31 - 1:  # at most 12.5% padding
-        return big
-    return ld
+def grid_stride(n):
+    """Node slots of a PDF grid: n rounded up to whole 64-node tiles."""
+    return _round_up(max(n, 1), 64)
 
 
-def aligned_empty(torch, numel, dtype, device, align=_STREAM_ALIGN):
+def aligned_empty(torch, numel, dtype, device, align=_GRID_ALIGN):
     """A 1-D tensor of ``numel`` elements whose first element is ``align``-aligned."""
     esize = torch.empty((), dtype=dtype).element_size()
     extra = align // esize
@@ -79,7 +72,7 @@ class Solver:
         N, R = lattice.n_fluid, lattice.n_runs
         self.n_fluid = N
         dtype = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[precision]
-        self.ldf = grid_stride(N, torch.empty((), dtype=dtype).element_size())
+        self.ldf = grid_stride(N)
         ngrids = 2 if pattern == "osnt" else 1
         dev = self.device
         with torch.cuda.device(dev):

@@ -99,6 +99,8 @@ def test_bench_stream_validation():
     assert L.lbm_bench_stream(0, vp(DUMMY), vp(DUMMY), -1, 0, None) == capi.LBM_EINVAL
     assert L.lbm_bench_stream(1, vp(DUMMY), vp(DUMMY), 10, 5, None) == capi.LBM_EINVAL
     assert L.lbm_bench_stream(0, vp(DUMMY + 8), vp(DUMMY), 10, 0, None) == capi.LBM_EINVAL
+    assert L.lbm_bench_stream(5, vp(DUMMY), vp(DUMMY), 100, 64, None) == capi.LBM_EINVAL
+    assert L.lbm_bench_stream(6, vp(DUMMY), vp(DUMMY), 100, 100, None) == capi.LBM_EINVAL
     assert L.lbm_bench_stream(0, vp(DUMMY), vp(DUMMY), 0, 0, None) == 0  # nothing to do
 
 
