@@ -94,28 +94,46 @@ def traffic_from(fetch_csv, write_csv, workload_name, command):
     import csv
 
     def load(path, counter):
+        # per kernel: (dispatch id, bytes) in launch order; the variants run
+        # one after the other, so a kernel shared by two variants (the odd step
+        # with and without the XCD remap) shows up as separate clusters of
+        # dispatch ids; each cluster is averaged on its own
         acc = {}
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
             k = kernel_key(r["Kernel_Name"])
-            acc.setdefault(k, []).append(float(r["Counter_Value"]) * 1024.0)
-        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+            acc.setdefault(k, []).append((int(r["Dispatch_Id"]), float(r["Counter_Value"]) * 1024.0))
+        out = {}
+        for k, v in acc.items():
+            v.sort()
+            clusters = [[v[0][1]]]
+            for (d0, _), (d1, b) in zip(v, v[1:]):
+                if d1 - d0 > 4:
+                    clusters.append([])
+                clusters[-1].append(b)
+            out[k] = [(sum(c) / len(c), len(c)) for c in clusters]
+        return out
 
     fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
     mask, p = __import__("lbm_inputs").workload(workload_name)
     n = int((mask == 0).sum())
     ld = (n + 63) // 64 * 64
     copy_bytes = 8 * 19 * ld  # read once and written once by the copy kernel
-    sf = copy_bytes / fetch["bench_copy"][0]
-    sw = copy_bytes / write["bench_copy"][0]
+    sf = copy_bytes / fetch["bench_copy"][0][0]
+    sw = copy_bytes / write["bench_copy"][0][0]
     kernels = {}
     for k in sorted(set(fetch) & set(write)):
         if k.startswith("bench_") or k.startswith("at::"):
             continue
-        fb, wb = fetch[k][0] * sf, write[k][0] * sw
+        # the first cluster belongs to the first variant that runs the kernel
+        fb, wb = fetch[k][0][0] * sf, write[k][0][0] * sw
         kernels[k] = {"fetch_bytes": int(fb), "write_bytes": int(wb), "hbm_bytes_per_launch": int(fb + wb),
-                      "dispatches": fetch[k][1]}
+                      "dispatches": fetch[k][0][1]}
+        if len(fetch[k]) > 1 and len(fetch[k]) == len(write[k]):
+            kernels[k]["later_clusters"] = [
+                {"fetch_bytes": int(f * sf), "write_bytes": int(w * sw), "dispatches": n}
+                for (f, n), (w, _) in zip(fetch[k][1:], write[k][1:])]
     doc = {"workload": workload_name, "source_digest": source_digest(),
            "scale": {"fetch": round(sf, 4), "write": round(sw, 4),
                      "reference": "copy micro-benchmark of %d bytes" % copy_bytes},
