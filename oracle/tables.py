@@ -21,6 +21,9 @@ Readings where the paper is silent:
   site is solid or outside the box (pull scheme, Sect. 4).
 * Run rule: node n > 0 continues the run of node n - 1 iff for every q the
   entry of n is the entry of n - 1 plus one, or both entries are -1.
+* Per-direction runs (a GPU encoding of the same idea, not in the paper):
+  the run rule applied to one direction q at a time. A node starts a run of
+  the paper's rule iff it starts a run of at least one direction.
 """
 
 from __future__ import annotations
@@ -199,6 +202,52 @@ def wave_tables(adj, run_start, wave=WAVE):
     per_wave = hb.sum(axis=1)
     base = (np.cumsum(per_wave) - per_wave - 1).astype(np.int32)
     return delta, bits, base
+
+
+def direction_heads(adj):
+    """Boolean (18, N): node n starts a run of direction q (the run rule of
+    Sect. 4.1 applied to the entries of direction q alone)."""
+    q, n = adj.shape
+    head = np.ones((q, n), dtype=bool)
+    if n > 1:
+        prev, cur = adj[:, :-1].astype(np.int64), adj[:, 1:].astype(np.int64)
+        same = ((prev >= 0) & (cur == prev + 1)) | ((prev < 0) & (cur < 0))
+        head[:, 1:] = ~same
+    return head
+
+
+def direction_tables(adj, wave=WAVE):
+    """Per-direction, per-wavefront RIA encoding.
+
+    The runs of direction q (q = 1..18) are numbered consecutively after those
+    of directions 1..q-1. dir_delta[r] = adj[q-1, head_r] - head_r (DELTA_SOLID
+    for -1) for run r, whose first node is head_r. For wave w and direction q
+    (row w, column q-1 of the (W, 18) tables):
+      dir_bits  has bit l set iff node wave*w + l starts a run of direction q;
+      dir_base  = (index of the first run of direction q) + (number of
+                  direction-q run heads below node wave*w) - 1.
+    Node wave*w + l then lies in run dir_base + popcount(dir_bits & bits 0..l)
+    of its direction, and its entry is the node index plus that run's delta.
+    """
+    nq, n = adj.shape
+    head = direction_heads(adj)
+    nw = -(-n // wave)
+    deltas, bits, base = [], np.zeros((nw, nq), dtype=np.uint64), np.zeros((nw, nq), dtype=np.int64)
+    first = 0
+    for q in range(nq):
+        h = np.flatnonzero(head[q])
+        a = adj[q, h].astype(np.int64)
+        deltas.append(np.where(a >= 0, a - h, DELTA_SOLID))
+        hw = np.zeros(nw * wave, dtype=bool)
+        hw[h] = True
+        hw = hw.reshape(nw, wave)
+        for l in range(wave):
+            bits[:, q] |= hw[:, l].astype(np.uint64) << np.uint64(l)
+        per_wave = hw.sum(axis=1)
+        base[:, q] = first + np.cumsum(per_wave) - per_wave - 1
+        first += len(h)
+    delta = np.concatenate(deltas).astype(np.int32) if nq else np.zeros(0, np.int32)
+    return delta, bits, base.astype(np.int32)
 
 
 def simd_fraction(run_start, vector=4):

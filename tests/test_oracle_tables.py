@@ -191,6 +191,47 @@ def test_runs_and_wave_tables_brute_force(order, block):
                 assert (adj[q, i] == -1) if d == tables.DELTA_SOLID else (adj[q, i] == i + d)
 
 
+@pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 2), ("morton", 0)])
+def test_direction_tables_brute_force(order, block):
+    # per-direction runs: the run rule for one direction at a time; decoding
+    # every entry from the tables alone must give the adjacency list back
+    for mask in tiny_masks() + [channel_mask(6, 9, 70)]:
+        if mask.min() == 1:
+            continue
+        nodes = tables.enumerate_nodes(mask, order, block)
+        adj = tables.adjacency(mask, (True, False, True), nodes)
+        n = adj.shape[1]
+        heads = tables.direction_heads(adj)
+        for q in range(18):
+            want = [0] + [i for i in range(1, n)
+                          if not ((adj[q, i - 1] >= 0 and adj[q, i] == adj[q, i - 1] + 1) or
+                                  (adj[q, i - 1] < 0 and adj[q, i] < 0))]
+            assert np.flatnonzero(heads[q]).tolist() == want
+        # the paper's run heads are the nodes where at least one direction breaks
+        assert np.flatnonzero(heads.any(axis=0)).tolist() == brute_heads(adj)[:-1]
+        delta, bits, base = tables.direction_tables(adj, wave=8)
+        assert len(delta) == heads.sum()
+        for i in range(n):
+            w, l = divmod(i, 8)
+            for q in range(18):
+                r = int(base[w, q]) + bin(int(bits[w, q]) & ((2 << l) - 1)).count("1")
+                assert heads[:q].sum() <= r < heads[:q + 1].sum()
+                d = int(delta[r])
+                assert (adj[q, i] == -1) if d == tables.DELTA_SOLID else (adj[q, i] == i + d)
+
+
+def test_direction_runs_of_open_periodic_box():
+    # 4^3 fully fluid, all axes periodic, x slowest: the upstream entry of
+    # direction q wraps once per line along every axis c_q moves on. Per
+    # direction that breaks runs twice per z-line (c_z != 0: 2 * 16), twice
+    # per x-plane (c_z = 0, c_y != 0: 2 * 4) or twice in the box (only c_x).
+    t = tables.build(np.zeros((4, 4, 4), np.uint8), (True, True, True))
+    heads = tables.direction_heads(t["adj"])
+    for q in range(1, 19):
+        want = 32 if C[q][2] else (8 if C[q][1] else 2)
+        assert heads[q - 1].sum() == want, q
+
+
 def test_morton_has_no_runs_in_open_box():
     # every step of a Morton curve changes more than one coordinate bit, so
     # no node continues a run on an all-fluid periodic box
