@@ -38,16 +38,21 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(kind, n, r, w, s=8):
-    """Algorithmic HBM bytes of one launch (PDFs read + written once, plus indices)."""
+def kernel_bytes(kind, n, idx, s=8):
+    """Algorithmic HBM bytes of one launch: the PDFs read and written once,
+    plus, for an indirect step, ``idx`` index bytes per node (72 for the
+    adjacency list; the run tables' bytes per node for RIA)."""
     pdf = 38 * s * n
     if kind == "even":
         return pdf
-    if kind in ("odd_ia", "osnt_ia"):
-        return pdf + 72 * n
-    if kind in ("odd_ria", "osnt_ria"):
-        return pdf + 72 * r + 12 * w
+    if kind in ("odd", "osnt"):
+        return pdf + idx * n
     raise KeyError(kind)
+
+
+# kernel names of the odd step per index source (as rocprofv3 prints them)
+ODD_KERNEL = {"adjacency": "aa_odd<double, IndexIA, false>", "runs": "aa_odd<double, IndexRIA, false>",
+              "direction": "aa_odd<double, IndexRIADir, false>"}
 
 
 def source_digest():
@@ -147,6 +152,7 @@ def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_rema
     from paper_1410_0412_amd import Solver
 
     s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=precision, xcd_remap=xcd_remap)
+    index = s.index
     s.init()
     s.step(2 * warmup)
     torch.cuda.synchronize()
@@ -165,7 +171,7 @@ def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_rema
     if not np.isfinite(tot.cpu().numpy()).all():
         raise RuntimeError("non-finite totals after the timed run")
     del s
-    return wall, d[0::2], d[1::2]
+    return wall, d[0::2], d[1::2], index
 
 
 def microbench(torch, n_nodes):
@@ -227,13 +233,14 @@ def order_sweep(torch, args):
         t0 = time.perf_counter()
         lat = Lattice(mask, p["periodic"], order, blk)
         tb = time.perf_counter() - t0
-        N, R, W = lat.n_fluid, lat.n_runs, lat.n_waves
+        N, R = lat.n_fluid, lat.n_runs
+        idx = lat.index_bytes()["runs"]
         row = {"fluid_nodes": N, "runs_per_node": round(R / N, 5), "lattice_build_s": round(tb, 2)}
         for prec in ("f64", "f32"):
-            wall, d_e, d_o = time_variant(torch, lat, p, "aa", True, prec, args.steps, args.warmup)
+            wall, d_e, d_o, _ = time_variant(torch, lat, p, "aa", True, prec, args.steps, args.warmup)
             sb = 8 if prec == "f64" else 4
             mflups = 2 * N * args.steps / wall / 1e6
-            bl = (kernel_bytes("even", N, R, W, sb) + kernel_bytes("odd_ria", N, R, W, sb)) / 2 / N
+            bl = (kernel_bytes("even", N, idx, sb) + kernel_bytes("odd", N, idx, sb)) / 2 / N
             row[prec] = {"mflups": round(mflups, 1), "even_us": round(float(np.mean(d_e)) * 1e6, 1),
                          "odd_us": round(float(np.mean(d_o)) * 1e6, 1), "loop_balance_B_per_FLUP": round(bl, 2),
                          "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4)}
@@ -280,7 +287,10 @@ def precision_study(torch, args):
         del s
     out = {"metric": "error of deviation storage vs the FP64 GPU path", "n_gpus": 1, "steps": steps,
            "data": "synthetic", "config": {"workload": args.workload, "fluid_nodes": lat.n_fluid,
-                                           "variant": "AA-RIA", "tau": p["tau"], "force": list(p["force"])},
+                                           "variant": "AA-RIA",
+            "ria_index": main_index,
+            "index_bytes_per_node": {k: round(v, 3) for k, v in idx_bytes.items()},
+            "direction_runs": lat.n_direction_runs, "tau": p["tau"], "force": list(p["force"])},
            "precisions": res}
     print(json.dumps(out), flush=True)
 
@@ -373,35 +383,43 @@ def main():
     r = R / N
     log("lattice N=%d R=%d r=%.4f built in %.2fs" % (N, R, r, t_build))
 
-    variants = [("aa", True, "f64", True), ("aa", True, "f32", True)]
+    idx_bytes = lat.index_bytes()
+    log("index bytes per node and indirect step", {k: round(v, 3) for k, v in idx_bytes.items()})
+    # RIA lines use the library's choice between the paper's runs and
+    # per-direction runs ("auto"); the paper's runs are also timed on their own
+    variants = [("aa", "auto", "f64", True), ("aa", "auto", "f32", True)]
     if not args.no_variants:
-        variants += [("aa", False, "f64", True), ("osnt", False, "f64", True), ("osnt", True, "f64", True),
-                     ("aa", True, "f16", True), ("aa", True, "f64", False)]
+        variants += [("aa", "runs", "f64", True), ("aa", False, "f64", True), ("osnt", False, "f64", True),
+                     ("osnt", "auto", "f64", True), ("osnt", "runs", "f64", True), ("aa", "auto", "f16", True),
+                     ("aa", "auto", "f64", False)]
+    names = {"auto": "ria", "runs": "ria_runs", False: "ia"}
     res = {}
     for pattern, ria, prec, remap in variants:
-        key = "%s_%s_%s%s" % (pattern, "ria" if ria else "ia", prec, "" if remap else "_no_xcd_remap")
+        key = "%s_%s_%s%s" % (pattern, names[ria], prec, "" if remap else "_no_xcd_remap")
         log("timing", key)
-        wall, d_a, d_b = time_variant(torch, lat, p, pattern, ria, prec, args.steps, args.warmup, remap)
+        wall, d_a, d_b, index = time_variant(torch, lat, p, pattern, ria, prec, args.steps, args.warmup, remap)
         mflups = 2 * N * args.steps / wall / 1e6
         sb = {"f64": 8, "f32": 4, "f16": 2}[prec]
+        idx = idx_bytes[index]
         if pattern == "aa":
-            kinds = ("even", "odd_ria" if ria else "odd_ia")
-            avg = (kernel_bytes(kinds[0], N, R, W, sb) + kernel_bytes(kinds[1], N, R, W, sb)) / 2
+            kinds = ("even", "odd")
+            avg = (kernel_bytes("even", N, idx, sb) + kernel_bytes("odd", N, idx, sb)) / 2
         else:
-            kinds = ("osnt_ria" if ria else "osnt_ia",) * 2
-            avg = kernel_bytes(kinds[0], N, R, W, sb)
+            kinds = ("osnt", "osnt_b")
+            avg = kernel_bytes("osnt", N, idx, sb)
         bl = avg / N
         res[key] = {
             "mflups": round(mflups, 1),
+            "index": index,
             "ms_per_time_step": round(wall / (2 * args.steps) * 1e3, 4),
             "kernel_us": {kinds[0]: round(float(np.mean(d_a)) * 1e6, 2),
-                          kinds[1] + ("" if kinds[0] != kinds[1] else "_b"): round(float(np.mean(d_b)) * 1e6, 2)},
+                          kinds[1]: round(float(np.mean(d_b)) * 1e6, 2)},
             "loop_balance_B_per_FLUP": round(bl, 3),
             "hbm_gbs_model": round(mflups * bl / 1e3, 1),
             "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4),
         }
         if key == "aa_ria_f64":
-            main_wall, main_odd = wall, d_b
+            main_wall, main_odd, main_index = wall, d_b, index
         log(key, res[key])
 
     micro = microbench(torch, N)
@@ -414,10 +432,11 @@ def main():
         row["frac_of_matched_roofline"] = round(row["mflups"] / (bw * 1e3 / row["loop_balance_B_per_FLUP"]), 4)
 
     aa = res["aa_ria_f64"]
-    odd_bytes = kernel_bytes("odd_ria", N, R, W)
+    odd_bytes = kernel_bytes("odd", N, idx_bytes[main_index])
     odd_s = float(np.mean(main_odd))
     achieved = odd_bytes / odd_s / 1e9
-    traffic = measured_traffic("aa_odd<double, IndexRIA, false>", WORKLOAD)
+    odd_kernel = ODD_KERNEL[main_index]
+    traffic = measured_traffic(odd_kernel, WORKLOAD)
     out = {
         "metric": METRIC,
         "value": aa["mflups"],
@@ -434,6 +453,9 @@ def main():
         "config": {
             "workload": WORKLOAD,
             "variant": "AA-RIA",
+            "ria_index": main_index,
+            "index_bytes_per_node": {k: round(v, 3) for k, v in idx_bytes.items()},
+            "direction_runs": lat.n_direction_runs,
             "step": "one AA cycle: direct even step + indirect odd step (2 time steps)",
             "fluid_nodes": N, "runs": R, "runs_per_node": round(r, 5),
             "porosity": round(float(1.0 - mask.mean()), 5),
@@ -443,7 +465,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "aa_odd<double, IndexRIA, false>",
+            "kernel": odd_kernel,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -461,6 +483,7 @@ def main():
             "matched_roofline_mflups": round(micro["U-19T"] * 1e3 / aa["loop_balance_B_per_FLUP"], 1),
             "frac_of_matched_roofline": aa["frac_of_matched_roofline"],
             "paper_model_B_l_aa_r": round(304 + 38 * r, 3),
+            "frac_of_paper_model_roofline": round(aa["mflups"] / (HBM_PEAK_GBS * 1e3 / (304 + 38 * r)), 4),
         },
         "fp32": {"value": res["aa_ria_f32"]["mflups"], "unit": "MFLUP/s",
                  "frac_of_hbm_roofline": res["aa_ria_f32"]["frac_of_hbm_roofline"],

@@ -57,6 +57,9 @@ enum { LBM_ORDER_LEX = 0, LBM_ORDER_MORTON = 1, LBM_ORDER_HILBERT = 2, LBM_ORDER
 enum { LBM_PATTERN_AA = 0, LBM_PATTERN_OSNT = 1 };
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
 enum { LBM_BGK = 0, LBM_TRT = 1 };
+/* Neighbour index source of a solver (lbm_params.ria): the adjacency list,
+ * the paper's runs (Sect. 4.1) or per-direction runs. */
+enum { LBM_INDEX_ADJ = 0, LBM_INDEX_RUNS = 1, LBM_INDEX_DIRECTION_RUNS = 2 };
 /* Solver flag: launch the AA odd step in plain tile order instead of giving
  * each XCD one contiguous range of tiles. */
 enum { LBM_FLAG_NO_XCD_REMAP = 1 };
@@ -132,6 +135,31 @@ int lbm_lattice_copy_runs(const lbm_lattice* lat, int32_t* run_start);
 int lbm_lattice_copy_wave_tables(const lbm_lattice* lat, int32_t* run_delta, int64_t ldr,
                                  uint64_t* head_bits, int32_t* run_base);
 
+/*
+ * Per-direction runs (a GPU encoding of the idea of Sect. 4.1, not part of
+ * the paper): the run rule applied to each direction q on its own, so a run
+ * of direction q only ends where the entries of q stop shifting by one (the
+ * paper's runs end where any direction does). Runs of direction q are
+ * numbered after those of directions 1..q-1; RD is their total.
+ * LBM_ERANGE if RD exceeds 2^31-1.
+ */
+int lbm_lattice_direction_runs(const lbm_lattice* lat, int64_t* n_dir_runs);
+
+/*
+ * Per-direction wave tables (any pointer may be NULL, then skipped):
+ * dir_delta  host int32[RD]: adj_q(h) - h for the run of direction q whose
+ *            first node is h, or INT32_MIN if adj_q(h) = -1.
+ * dir_bits   host uint64[18*W]; word 18w + q-1 has bit l set iff node 64w+l
+ *            starts a run of direction q.
+ * dir_base   host int32[18*W]; entry 18w + q-1 = (index of the first run of
+ *            direction q) + (direction-q run starts below node 64w) - 1.
+ * For node n = 64w+l: k = 18w + q-1, r = dir_base[k] +
+ * popcount(dir_bits[k] & bits 0..l), and adj_q(n) = n + dir_delta[r].
+ * LBM_ERANGE if RD exceeds 2^31-1.
+ */
+int lbm_lattice_copy_direction_tables(const lbm_lattice* lat, int32_t* dir_delta,
+                                      uint64_t* dir_bits, int32_t* dir_base);
+
 void lbm_lattice_free(lbm_lattice* lat);
 
 /* ====================================================================== */
@@ -143,7 +171,9 @@ typedef struct lbm_params {
   double force[3];   /* constant body-force density F                       */
   double rho0;       /* reference density of deviation storage (> 0)        */
   int32_t pattern;   /* LBM_PATTERN_AA or LBM_PATTERN_OSNT                   */
-  int32_t ria;       /* 0: adjacency list; 1: RIA wave tables                */
+  int32_t ria;       /* LBM_INDEX_ADJ: adjacency list; LBM_INDEX_RUNS: RIA
+                        wave tables; LBM_INDEX_DIRECTION_RUNS: per-direction
+                        RIA tables                                           */
   int32_t precision; /* LBM_F64: FP64 storage and arithmetic. LBM_F32: the
                         grid stores d_q = f_q - w_q*rho0 in FP32. LBM_F16: it
                         stores d_q * 2^f16_scale_log2 / w_q in FP16. Both
@@ -151,13 +181,13 @@ typedef struct lbm_params {
                         export/import are FP64.                              */
   int32_t flags;     /* LBM_FLAG_NO_XCD_REMAP, or 0                          */
   int64_t n_fluid;   /* N                                                    */
-  int64_t n_runs;    /* R (RIA only)                                         */
+  int64_t n_runs;    /* R (LBM_INDEX_RUNS) or RD (LBM_INDEX_DIRECTION_RUNS) */
   int64_t ldf;       /* node slots of the grid: >= N, a multiple of 64,
                         19*ldf <= 2^31 - 1. Grid layout (tile-major SoA):
                         direction q of node n = 64t + l is element
                         (19t + q)*64 + l; a grid holds 19*ldf elements.     */
   int64_t lda;       /* adjacency row stride (>= N), adjacency only          */
-  int64_t ldr;       /* run_delta row stride (>= R), RIA only                */
+  int64_t ldr;       /* run_delta row stride (>= R), LBM_INDEX_RUNS only     */
   int32_t f16_scale_log2; /* FP16 storage scale exponent s, in [-24, 24]     */
   int32_t collision; /* LBM_BGK, or LBM_TRT (two relaxation times, Sect. 2):
                         f*_q = f_q - w+ (f+_q - feq+_q) - w- (f-_q - feq-_q)
@@ -170,10 +200,11 @@ typedef struct lbm_buffers {
                                  storage type (double, float or IEEE half)
                                  each, tile-major (see ldf); pdf[1] only for
                                  OS-NT                                       */
-  const int32_t* adj;         /* device [18][lda] (ria = 0)                  */
-  const int32_t* run_delta;   /* device [18][ldr] (ria = 1)                  */
-  const uint64_t* head_bits;  /* device [W]       (ria = 1)                  */
-  const int32_t* run_base;    /* device [W]       (ria = 1)                  */
+  const int32_t* adj;         /* device [18][lda] (LBM_INDEX_ADJ)            */
+  const int32_t* run_delta;   /* device [18][ldr] (LBM_INDEX_RUNS), or
+                                 dir_delta [RD] (LBM_INDEX_DIRECTION_RUNS)   */
+  const uint64_t* head_bits;  /* device [W], or dir_bits [W][18]             */
+  const int32_t* run_base;    /* device [W], or dir_base [W][18]             */
   const double* solid_frac;   /* device [N] partial-bounce-back solid
                                  fraction ns in [0, 1] per node, or NULL.
                                  With it every step applies

@@ -17,6 +17,7 @@ ORDERS = {"lex": 0, "morton": 1, "hilbert": 2, "hilbert_ls": 3}
 PATTERNS = {"aa": 0, "osnt": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2}
 FLAG_NO_XCD_REMAP = 1
+INDEX = {"adjacency": 0, "runs": 1, "direction": 2}
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
 c_i64p = ctypes.POINTER(ctypes.c_int64)
@@ -84,6 +85,8 @@ def lib():
         "lbm_lattice_copy_adjacency": (ctypes.c_int, [vp, vp, ctypes.c_int64]),
         "lbm_lattice_copy_runs": (ctypes.c_int, [vp, vp]),
         "lbm_lattice_copy_wave_tables": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
+        "lbm_lattice_direction_runs": (ctypes.c_int, [vp, c_i64p]),
+        "lbm_lattice_copy_direction_tables": (ctypes.c_int, [vp, vp, vp, vp]),
         "lbm_lattice_free": (None, [vp]),
         "lbm_solver_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), c_i64p]),
         "lbm_solver_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(Buffers), vp,
@@ -114,7 +117,7 @@ def lib():
 EXPORTED = [
     "lbm_last_error", "lbm_lattice_build", "lbm_lattice_sizes", "lbm_lattice_copy_nodes",
     "lbm_lattice_copy_adjacency", "lbm_lattice_copy_runs", "lbm_lattice_copy_wave_tables",
-    "lbm_lattice_free", "lbm_solver_workspace_bytes", "lbm_solver_create", "lbm_solver_set_stream",
+    "lbm_lattice_direction_runs", "lbm_lattice_copy_direction_tables", "lbm_lattice_free", "lbm_solver_workspace_bytes", "lbm_solver_create", "lbm_solver_set_stream",
     "lbm_solver_init_equilibrium", "lbm_solver_step", "lbm_solver_time", "lbm_solver_moments",
     "lbm_solver_export_pdfs", "lbm_solver_import_pdfs", "lbm_solver_free", "lbm_bench_stream",
     "lbm_solver_set_time", "lbm_solver_weighted_momentum", "lbm_adjoint_seed_momentum", "lbm_adjoint_step",

@@ -88,6 +88,38 @@ struct IndexRIA {
   }
 };
 
+// Per-direction RIA: the run rule applied to one direction at a time, so a
+// run of direction q only breaks where the entries of q stop shifting by one.
+// On fragmented porous media a node then rarely needs fresh deltas for all 18
+// directions: the tables hold 4 B per direction run plus 12 B per wave and
+// direction, against 72 B per run of the joint encoding. Wave w reads its 18
+// head words and 18 bases as wave-uniform values; a direction whose run spans
+// the whole wave fetches its delta with a scalar load.
+struct IndexRIADir {
+  const int32_t* __restrict__ delta;       // [RD]
+  const uint64_t* __restrict__ head_bits;  // [W][18]
+  const int32_t* __restrict__ run_base;    // [W][18]
+
+  __device__ __forceinline__ void get(int32_t n, int32_t (&a)[18]) const {
+    const int32_t w = __builtin_amdgcn_readfirstlane(n >> 6);
+    const uint64_t* bw = head_bits + w * 18;
+    const int32_t* rw = run_base + w * 18;
+    const int lane = n & 63;
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+#pragma unroll
+    for (int q = 0; q < 18; ++q) {
+      const uint64_t bits = bw[q];
+      int32_t d;
+      if ((bits >> 1) == 0) {
+        d = delta[__builtin_amdgcn_readfirstlane(rw[q] + (int32_t)(bits & 1))];
+      } else {
+        d = delta[rw[q] + __popcll(bits & upto)];
+      }
+      a[q] = d == INT32_MIN ? -1 : n + d;
+    }
+  }
+};
+
 // Slots are 32-bit element offsets into the grid (the host guarantees
 // 19 * ldf < 2^31 elements). Per lane a slot costs a compare, two selects
 // and a few integer operations, with no branch.

@@ -31,6 +31,11 @@ struct lbm_lattice {
   std::vector<int32_t> run_delta;   // [18][R]
   std::vector<uint64_t> head_bits;  // [W]
   std::vector<int32_t> run_base;    // [W]
+  // per-direction runs; RD < 0 when their count does not fit int32
+  int64_t RD = 0;
+  std::vector<int32_t> dir_delta;   // [RD]
+  std::vector<uint64_t> dir_bits;   // [W][18]
+  std::vector<int32_t> dir_base;    // [W][18]
 };
 
 namespace {
@@ -258,6 +263,67 @@ void build_runs(lbm_lattice* L) {
   }
 }
 
+// Per-direction runs: the run rule above applied to one direction at a time.
+// Runs of direction q are numbered after those of directions 1..q-1.
+void build_direction_runs(lbm_lattice* L) {
+  const int64_t N = L->N, W = L->W;
+  const int32_t* A = L->adj.data();
+  L->dir_bits.assign((size_t)(W * 18), 0);
+  L->dir_base.assign((size_t)(W * 18), 0);
+  parallel_for(W, [&](int64_t lo, int64_t hi) {
+    for (int64_t w = lo; w < hi; ++w) {
+      const int64_t n0 = w * kWave, n1 = std::min(N, n0 + kWave);
+      for (int q = 0; q < 18; ++q) {
+        const int32_t* a = A + (size_t)q * N;
+        uint64_t bits = 0;
+        for (int64_t n = n0; n < n1; ++n) {
+          const bool cont = n > 0 && ((a[n - 1] >= 0) ? (a[n] == a[n - 1] + 1) : (a[n] < 0));
+          if (!cont) bits |= (uint64_t)1 << (n - n0);
+        }
+        L->dir_bits[(size_t)w * 18 + q] = bits;
+      }
+    }
+  });
+  int64_t first = 0;
+  for (int q = 0; q < 18; ++q) {
+    int64_t below = 0;
+    for (int64_t w = 0; w < W; ++w) {
+      const int64_t base = first + below - 1;
+      if (base > INT32_MAX) {
+        L->RD = -1;
+        L->dir_bits.clear();
+        L->dir_base.clear();
+        return;
+      }
+      L->dir_base[(size_t)w * 18 + q] = (int32_t)base;
+      below += __builtin_popcountll(L->dir_bits[(size_t)w * 18 + q]);
+    }
+    first += below;
+  }
+  if (first > INT32_MAX) {
+    L->RD = -1;
+    L->dir_bits.clear();
+    L->dir_base.clear();
+    return;
+  }
+  L->RD = first;
+  L->dir_delta.assign((size_t)first, INT32_MIN);
+  parallel_for(W, [&](int64_t lo, int64_t hi) {
+    for (int64_t w = lo; w < hi; ++w)
+      for (int q = 0; q < 18; ++q) {
+        const int32_t* a = A + (size_t)q * N;
+        uint64_t bits = L->dir_bits[(size_t)w * 18 + q];
+        int64_t r = (int64_t)L->dir_base[(size_t)w * 18 + q];
+        while (bits) {
+          const int l = __builtin_ctzll(bits);
+          bits &= bits - 1;
+          const int64_t h = w * kWave + l;
+          L->dir_delta[(size_t)++r] = a[h] >= 0 ? (int32_t)(a[h] - h) : INT32_MIN;
+        }
+      }
+  });
+}
+
 }  // namespace
 
 extern "C" {
@@ -285,6 +351,7 @@ int lbm_lattice_build(const uint8_t* solid, int32_t nx, int32_t ny, int32_t nz,
     L->N = (int64_t)L->node_voxel.size();
     build_adjacency(L, periodic_mask);
     build_runs(L);
+    build_direction_runs(L);
   } catch (const std::bad_alloc&) {
     delete L;
     return fail(LBM_ENOMEM, "out of host memory building the lattice");
@@ -340,6 +407,25 @@ int lbm_lattice_copy_wave_tables(const lbm_lattice* L, int32_t* run_delta, int64
   }
   if (head_bits && L->W) std::memcpy(head_bits, L->head_bits.data(), sizeof(uint64_t) * L->W);
   if (run_base && L->W) std::memcpy(run_base, L->run_base.data(), sizeof(int32_t) * L->W);
+  return LBM_OK;
+}
+
+int lbm_lattice_direction_runs(const lbm_lattice* L, int64_t* n_dir_runs) {
+  clear_error();
+  if (!L || !n_dir_runs) return fail(LBM_EINVAL, "null pointer");
+  if (L->RD < 0) return fail(LBM_ERANGE, "per-direction run count exceeds 2^31-1");
+  *n_dir_runs = L->RD;
+  return LBM_OK;
+}
+
+int lbm_lattice_copy_direction_tables(const lbm_lattice* L, int32_t* dir_delta, uint64_t* dir_bits,
+                                      int32_t* dir_base) {
+  clear_error();
+  if (!L) return fail(LBM_EINVAL, "null lattice");
+  if (L->RD < 0) return fail(LBM_ERANGE, "per-direction run count exceeds 2^31-1");
+  if (dir_delta && L->RD) std::memcpy(dir_delta, L->dir_delta.data(), sizeof(int32_t) * L->RD);
+  if (dir_bits && L->W) std::memcpy(dir_bits, L->dir_bits.data(), sizeof(uint64_t) * 18 * L->W);
+  if (dir_base && L->W) std::memcpy(dir_base, L->dir_base.data(), sizeof(int32_t) * 18 * L->W);
   return LBM_OK;
 }
 

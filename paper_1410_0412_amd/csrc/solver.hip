@@ -285,6 +285,19 @@ IndexIA index_ia(const lbm_solver* s) { return IndexIA{s->b.adj, (int32_t)s->p.l
 IndexRIA index_ria(const lbm_solver* s) {
   return IndexRIA{s->b.run_delta, s->b.head_bits, s->b.run_base, (int32_t)s->p.ldr};
 }
+IndexRIADir index_ria_dir(const lbm_solver* s) {
+  return IndexRIADir{s->b.run_delta, s->b.head_bits, s->b.run_base};
+}
+
+// Call go(idx) with the neighbour index source of the solver.
+template <class Go>
+void with_index(const lbm_solver* s, Go&& go) {
+  switch (s->p.ria) {
+    case LBM_INDEX_RUNS: go(index_ria(s)); break;
+    case LBM_INDEX_DIRECTION_RUNS: go(index_ria_dir(s)); break;
+    default: go(index_ia(s)); break;
+  }
+}
 
 // Layout of f(t) in the current grid.
 int current_layout(const lbm_solver* s) {
@@ -299,12 +312,7 @@ void* current_grid(const lbm_solver* s) {
 // Call fn(S*, idx) with the storage type and index source of the solver.
 template <class Fn>
 void dispatch(const lbm_solver* s, void* grid, Fn&& fn) {
-  auto with_idx = [&](auto* typed) {
-    if (s->p.ria)
-      fn(typed, index_ria(s));
-    else
-      fn(typed, index_ia(s));
-  };
+  auto with_idx = [&](auto* typed) { with_index(s, [&](auto idx) { fn(typed, idx); }); };
   switch (s->p.precision) {
     case LBM_F64: with_idx((double*)grid); break;
     case LBM_F32: with_idx((float*)grid); break;
@@ -355,10 +363,7 @@ void launch_step_pbb(lbm_solver* s, int32_t N) {
       hipLaunchKernelGGL((aa_step_pbb<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N,
                          idx, s->c, s->b.solid_frac);
   };
-  if (s->p.ria)
-    go(index_ria(s));
-  else
-    go(index_ia(s));
+  with_index(s, go);
 }
 
 int launch_step(lbm_solver* s) {
@@ -384,7 +389,8 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
   if (!std::isfinite(p->rho0) || !(p->rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be positive");
   if (p->pattern != LBM_PATTERN_AA && p->pattern != LBM_PATTERN_OSNT)
     return fail(LBM_EINVAL, "unknown pattern %d", p->pattern);
-  if (p->ria != 0 && p->ria != 1) return fail(LBM_EINVAL, "ria must be 0 or 1");
+  if (p->ria != LBM_INDEX_ADJ && p->ria != LBM_INDEX_RUNS && p->ria != LBM_INDEX_DIRECTION_RUNS)
+    return fail(LBM_EINVAL, "ria must be 0, 1 or 2");
   if (p->precision != LBM_F64 && p->precision != LBM_F32 && p->precision != LBM_F16)
     return fail(LBM_EINVAL, "unknown precision %d", p->precision);
   if (p->flags & ~LBM_FLAG_NO_XCD_REMAP) return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
@@ -400,7 +406,12 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
   if (p->pattern == LBM_PATTERN_OSNT && !b->pdf[1]) return fail(LBM_EINVAL, "OS-NT needs pdf[1]");
   if (b->solid_frac && (p->pattern != LBM_PATTERN_AA || p->precision != LBM_F64 || p->collision != LBM_BGK))
     return fail(LBM_EINVAL, "partial bounce-back needs the AA pattern, FP64 and BGK");
-  if (p->ria) {
+  if (p->ria == LBM_INDEX_DIRECTION_RUNS) {
+    if (p->n_runs < 0 || (p->n_fluid > 0 && p->n_runs < 18)) return fail(LBM_EINVAL, "n_runs invalid");
+    if (p->n_runs > INT32_MAX) return fail(LBM_ERANGE, "per-direction run count exceeds int32");
+    if (p->n_fluid > 0 && (!b->run_delta || !b->head_bits || !b->run_base))
+      return fail(LBM_EINVAL, "per-direction RIA needs run_delta, head_bits and run_base");
+  } else if (p->ria == LBM_INDEX_RUNS) {
     if (p->n_runs < 0 || (p->n_fluid > 0 && p->n_runs < 1)) return fail(LBM_EINVAL, "n_runs invalid");
     if (p->ldr < p->n_runs) return fail(LBM_EINVAL, "ldr < n_runs");
     if (p->ldr > (int64_t)INT32_MAX / 18) return fail(LBM_ERANGE, "18 * ldr exceeds int32");
@@ -621,10 +632,7 @@ int lbm_adjoint_seed_momentum(lbm_solver* s, const double* weight, int32_t axis,
       hipLaunchKernelGGL((adjoint_seed<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, lam, N,
                          idx, weight, (int)axis);
   };
-  if (s->p.ria)
-    go(index_ria(s));
-  else
-    go(index_ia(s));
+  with_index(s, go);
   return device_status("adjoint_seed_momentum");
 }
 
@@ -645,10 +653,7 @@ int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, d
       hipLaunchKernelGGL((aa_adjoint<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, fwd, lam, N,
                          idx, s->c, s->b.solid_frac, grad);
   };
-  if (s->p.ria)
-    go(index_ria(s));
-  else
-    go(index_ia(s));
+  with_index(s, go);
   return device_status("adjoint_step");
 }
 

@@ -83,3 +83,30 @@ class Lattice:
     @property
     def runs_per_node(self):
         return self.n_runs / max(self.n_fluid, 1)
+
+    @property
+    def n_direction_runs(self):
+        """RD: total number of per-direction runs (all 18 directions)."""
+        if getattr(self, "_rd", None) is None:
+            rd = ctypes.c_int64()
+            _capi.check(_capi.lib().lbm_lattice_direction_runs(self._h, ctypes.byref(rd)))
+            self._rd = rd.value
+        return self._rd
+
+    def direction_tables(self):
+        """(dir_delta int32 (RD,), dir_bits uint64 (W, 18), dir_base int32 (W, 18))."""
+        delta = np.empty(self.n_direction_runs, dtype=np.int32)
+        bits = np.empty((self.n_waves, 18), dtype=np.uint64)
+        base = np.empty((self.n_waves, 18), dtype=np.int32)
+        _capi.check(_capi.lib().lbm_lattice_copy_direction_tables(self._h, _ptr(delta), _ptr(bits),
+                                                                  _ptr(base)))
+        return delta, bits, base
+
+    def index_bytes(self):
+        """Index bytes per node of one indirect step, per index source: the
+        adjacency list (72), the paper's runs (72 per run + 12 per 64-node
+        wave) and per-direction runs (4 per run + 12 per wave and direction)."""
+        N = max(self.n_fluid, 1)
+        return {"adjacency": 72.0,
+                "runs": (72.0 * self.n_runs + 12.0 * self.n_waves) / N,
+                "direction": (4.0 * self.n_direction_runs + 216.0 * self.n_waves) / N}

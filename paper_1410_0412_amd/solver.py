@@ -39,11 +39,41 @@ def aligned_empty(torch, numel, dtype, device, align=_GRID_ALIGN):
     return base[off:off + numel]
 
 
+def choose_index(lattice, pattern="aa", precision="f64", margin=0.02):
+    """Index source for ``ria="auto"``: per-direction runs when their index
+    bytes undercut the paper's runs by at least ``margin`` of the loop balance
+    (bytes per FLUP with the paper's runs), else the paper's runs. The AA
+    pattern pays the index in every second step, OS-NT in every step."""
+    try:
+        b = lattice.index_bytes()
+    except Exception:  # per-direction tables unavailable (run count > 2^31-1)
+        return "runs"
+    s = {"f64": 8, "f32": 4, "f16": 2}[precision]
+    share = 0.5 if pattern == "aa" else 1.0
+    balance = 38.0 * s + share * b["runs"]
+    return "direction" if share * (b["runs"] - b["direction"]) >= margin * balance else "runs"
+
+
+def _index_source(ria, lattice, pattern, precision):
+    if ria is True or ria == "runs":
+        return "runs"
+    if ria is False or ria == "adjacency":
+        return "adjacency"
+    if ria == "direction":
+        return "direction"
+    if ria == "auto":
+        return choose_index(lattice, pattern, precision)
+    raise ValueError("ria must be True, False, 'runs', 'adjacency', 'direction' or 'auto'")
+
+
 class Solver:
     """D3Q19 BGK solver on a :class:`Lattice`.
 
     pattern    "aa" (one grid) or "osnt" (two grids, pull).
-    ria        True: RIA wave tables; False: adjacency list.
+    ria        Neighbour index source. True or "runs": the paper's RIA runs
+               (Sect. 4.1) as per-wavefront tables; False or "adjacency": the
+               adjacency list; "direction": per-direction runs; "auto": the
+               choice of :func:`choose_index`.
     precision  "f64" (FP64 storage and arithmetic), "f32" or "f16"
                (storage of deviations from the rest state, FP32 arithmetic).
     f16_scale_log2  FP16 storage holds d_q * 2^s / w_q (default s = 10).
@@ -67,7 +97,8 @@ class Solver:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.lattice = lattice
         self.pattern = pattern
-        self.ria = bool(ria)
+        self.index = _index_source(ria, lattice, pattern, precision)
+        self.ria = self.index != "adjacency"
         self.precision = precision
         N, R = lattice.n_fluid, lattice.n_runs
         self.n_fluid = N
@@ -80,12 +111,18 @@ class Solver:
             self.adj = self.run_delta = self.head_bits = self.run_base = None
             self.solid_frac = torch.zeros(max(N, 1), dtype=torch.float64, device=dev) if pbb else None
             lda = ldr = 0
-            if self.ria:
+            if self.index == "runs":
                 ldr = _round_up(max(R, 1), 64)
                 delta, bits, base = lattice.wave_tables(ldr)
                 self.run_delta = torch.from_numpy(delta).to(dev)
                 self.head_bits = torch.from_numpy(bits.view(np.int64)).to(dev)
                 self.run_base = torch.from_numpy(base).to(dev)
+            elif self.index == "direction":
+                R = lattice.n_direction_runs
+                delta, bits, base = lattice.direction_tables()
+                self.run_delta = torch.from_numpy(delta).to(dev)
+                self.head_bits = torch.from_numpy(bits.reshape(-1).view(np.int64)).to(dev)
+                self.run_base = torch.from_numpy(base.reshape(-1)).to(dev)
             else:
                 lda = _round_up(max(N, 1), 64)
                 self.adj = torch.from_numpy(lattice.adjacency(lda)).to(dev)
@@ -95,7 +132,7 @@ class Solver:
                 p.force[a] = float(force[a])
             p.rho0 = float(rho0)
             p.pattern = _capi.PATTERNS[pattern]
-            p.ria = int(self.ria)
+            p.ria = _capi.INDEX[self.index]
             p.precision = _capi.PRECISIONS[precision]
             p.flags = 0 if xcd_remap else _capi.FLAG_NO_XCD_REMAP
             p.n_fluid, p.n_runs, p.ldf, p.lda, p.ldr = N, R, self.ldf, lda, ldr

@@ -27,4 +27,6 @@ def normwise_u_error(u_gpu, u_ref):
     return d / np.sqrt((u_ref ** 2).sum(0)).max()
 
 
-VARIANTS = [("aa", False), ("aa", True), ("osnt", False), ("osnt", True)]
+#: (pattern, index source): adjacency list, the paper's runs, per-direction runs
+VARIANTS = [("aa", False), ("aa", True), ("aa", "direction"),
+            ("osnt", False), ("osnt", True), ("osnt", "direction")]

@@ -51,6 +51,7 @@ def create(p, b, ws_bytes=None):
 def test_valid_parameters_create():
     assert create(params(), buffers()) == 0
     assert create(params(ria=1), buffers()) == 0
+    assert create(params(ria=2, n_runs=18 * 3), buffers()) == 0
     assert create(params(pattern=1, precision=2, collision=1, trt_magic=0.1875), buffers()) == 0
 
 
@@ -60,7 +61,9 @@ def test_valid_parameters_create():
     (dict(force=(float("inf"), 0, 0)), capi.LBM_EINVAL),
     (dict(rho0=0.0), capi.LBM_EINVAL),
     (dict(pattern=2), capi.LBM_EINVAL),
-    (dict(ria=2), capi.LBM_EINVAL),
+    (dict(ria=3), capi.LBM_EINVAL),
+    (dict(ria=2, n_runs=17), capi.LBM_EINVAL),   # every direction has at least one run
+    (dict(ria=2, n_runs=2 ** 31), capi.LBM_ERANGE),
     (dict(precision=3), capi.LBM_EINVAL),
     (dict(flags=2), capi.LBM_EINVAL),
     (dict(collision=1, trt_magic=0.0), capi.LBM_EINVAL),
@@ -82,6 +85,8 @@ def test_invalid_parameters(kw, code):
 def test_missing_buffers_and_workspace():
     assert create(params(), buffers(adj=None)) == capi.LBM_EINVAL
     assert create(params(ria=1), buffers(run_delta=None)) == capi.LBM_EINVAL
+    for k in ("run_delta", "head_bits", "run_base"):
+        assert create(params(ria=2, n_runs=18), buffers(**{k: None})) == capi.LBM_EINVAL
     assert create(params(pattern=1), buffers(pdf=(ctypes.c_void_p * 2)(DUMMY, None))) == capi.LBM_EINVAL
     assert create(params(), buffers(), ws_bytes=8) == capi.LBM_EINVAL
 

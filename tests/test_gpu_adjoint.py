@@ -33,7 +33,7 @@ def nodes_of(lat, field):
     return field.reshape(-1)[lat.node_voxel().astype(np.int64)]
 
 
-@pytest.mark.parametrize("ria", [False, True])
+@pytest.mark.parametrize("ria", [False, True, "direction"])
 def test_pbb_forward_every_step(small, ria):
     mask, ns, _ = small
     tau, F = 0.8, (1e-5, 0, 0)
@@ -56,7 +56,7 @@ def test_pbb_zero_fraction_is_plain_step(small):
     assert np.array_equal(a.export_pdfs().cpu().numpy(), b.export_pdfs().cpu().numpy())
 
 
-@pytest.mark.parametrize("ria", [False, True])
+@pytest.mark.parametrize("ria", [False, True, "direction"])
 @pytest.mark.parametrize("every", [1, 5, 12])
 def test_gradient_matches_autograd(small, ria, every):
     from paper_1410_0412_amd import outlet_flux

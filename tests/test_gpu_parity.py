@@ -28,7 +28,7 @@ def spheres32():
 @pytest.mark.parametrize("pattern,ria", VARIANTS)
 def test_spheres32_100_steps(spheres32, pattern, ria):
     mask, p, f_ref, rho_ref, u_ref = spheres32
-    print("case spheres-32", pattern, "ria" if ria else "ia", flush=True)
+    print("case spheres-32", pattern, ria, flush=True)
     lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], pattern, ria)
     s.init()
     s.step(p["steps"])

@@ -1,6 +1,7 @@
 """The C++ lattice builder (product path) must reproduce the oracle's integer
-tables bit for bit: enumeration, adjacency, runs and wave tables. Runs on the
-CPU (the builder is host code of the library)."""
+tables bit for bit: enumeration, adjacency, runs, wave tables and the
+per-direction run tables. Runs on the CPU (the builder is host code of the
+library)."""
 import ctypes
 import os
 import re
@@ -29,6 +30,12 @@ def compare(mask, periodic, order, block):
     assert np.array_equal(d, ref["run_delta"])
     assert np.array_equal(b, ref["head_bits"])
     assert np.array_equal(base, ref["run_base"])
+    dd, db, dbase = L.direction_tables()
+    rd, rb, rbase = tables.direction_tables(ref["adj"])
+    assert L.n_direction_runs == len(rd)
+    assert np.array_equal(dd, rd)
+    assert np.array_equal(db, rb)
+    assert np.array_equal(dbase, rbase)
     return L
 
 
