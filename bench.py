@@ -219,7 +219,7 @@ def cpu_baseline(mask, p, steps=2):
 def order_sweep(torch, args):
     """Sect. 5.6 analogue: AA-RIA throughput and run density per enumeration."""
     from lbm_inputs import workload
-    from paper_1410_0412_amd import Lattice
+    from paper_1410_0412_amd import Lattice, choose_index
 
     log("generating", args.workload)
     mask, p = workload(args.workload, seed=args.seed)
@@ -234,16 +234,24 @@ def order_sweep(torch, args):
         lat = Lattice(mask, p["periodic"], order, blk)
         tb = time.perf_counter() - t0
         N, R = lat.n_fluid, lat.n_runs
-        idx = lat.index_bytes()["runs"]
-        row = {"fluid_nodes": N, "runs_per_node": round(R / N, 5), "lattice_build_s": round(tb, 2)}
-        for prec in ("f64", "f32"):
-            wall, d_e, d_o, _ = time_variant(torch, lat, p, "aa", True, prec, args.steps, args.warmup)
-            sb = 8 if prec == "f64" else 4
-            mflups = 2 * N * args.steps / wall / 1e6
-            bl = (kernel_bytes("even", N, idx, sb) + kernel_bytes("odd", N, idx, sb)) / 2 / N
-            row[prec] = {"mflups": round(mflups, 1), "even_us": round(float(np.mean(d_e)) * 1e6, 1),
-                         "odd_us": round(float(np.mean(d_o)) * 1e6, 1), "loop_balance_B_per_FLUP": round(bl, 2),
-                         "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4)}
+        ib = lat.index_bytes()
+        row = {"fluid_nodes": N, "runs_per_node": round(R / N, 5), "lattice_build_s": round(tb, 2),
+               "index_bytes_per_node": {k: round(v, 3) for k, v in ib.items()}}
+        # the paper's runs, then per-direction runs; "auto" names the choice
+        # the library makes between the two
+        row["auto"] = {prec: choose_index(lat, "aa", prec) for prec in ("f64", "f32")}
+        for ria in ("runs", "direction"):
+            for prec in ("f64", "f32"):
+                wall, d_e, d_o, index = time_variant(torch, lat, p, "aa", ria, prec, args.steps, args.warmup)
+                key = prec if ria == "runs" else prec + "_direction"
+                sb = 8 if prec == "f64" else 4
+                mflups = 2 * N * args.steps / wall / 1e6
+                bl = (kernel_bytes("even", N, ib[index], sb) + kernel_bytes("odd", N, ib[index], sb)) / 2 / N
+                row[key] = {"index": index, "mflups": round(mflups, 1),
+                            "even_us": round(float(np.mean(d_e)) * 1e6, 1),
+                            "odd_us": round(float(np.mean(d_o)) * 1e6, 1),
+                            "loop_balance_B_per_FLUP": round(bl, 2),
+                            "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4)}
         log(spec, row)
         out["orders"][spec] = row
         del lat
@@ -287,10 +295,8 @@ def precision_study(torch, args):
         del s
     out = {"metric": "error of deviation storage vs the FP64 GPU path", "n_gpus": 1, "steps": steps,
            "data": "synthetic", "config": {"workload": args.workload, "fluid_nodes": lat.n_fluid,
-                                           "variant": "AA-RIA",
-            "ria_index": main_index,
-            "index_bytes_per_node": {k: round(v, 3) for k, v in idx_bytes.items()},
-            "direction_runs": lat.n_direction_runs, "tau": p["tau"], "force": list(p["force"])},
+                                           "variant": "AA-RIA (paper's runs)", "tau": p["tau"],
+                                           "force": list(p["force"])},
            "precisions": res}
     print(json.dumps(out), flush=True)
 
