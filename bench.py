@@ -200,7 +200,25 @@ def microbench(torch, n_nodes):
     return out
 
 
-def cpu_baseline(mask, p, steps=2):
+def host_cpu():
+    """Model name and logical CPU counts of the host (as the OS reports them)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(mask, p, steps=6):
     from oracle import dense
 
     solid = mask.astype(bool)
@@ -212,8 +230,9 @@ def cpu_baseline(mask, p, steps=2):
     n = int((~solid).sum())
     return {"value": round(n * steps / dt / 1e6, 4), "unit": "MFLUP/s", "cores": 1, "kind": "oracle",
             "sample": "%d time steps of the full-array FP64 numpy oracle on the same %s lattice "
-                      "(single process, one thread; it updates all %d cells, MFLUP/s counts the %d fluid nodes)"
-                      % (steps, WORKLOAD, solid.size, n)}
+                      "(single process, one thread; it updates all %d cells, MFLUP/s counts the %d fluid nodes), "
+                      "%.1f s" % (steps, WORKLOAD, solid.size, n, dt),
+            "host": host_cpu()}
 
 
 def order_sweep(torch, args):
