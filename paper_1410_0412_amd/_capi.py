@@ -72,7 +72,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("liblbm_sparse.so is not built (run __graft_entry__.build()): %s" % LIB_PATH)
+        raise ImportError("liblbm_sparse.so is not built (run python paper_1410_0412_amd/build.py): %s" % LIB_PATH)
     L = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     sig = {

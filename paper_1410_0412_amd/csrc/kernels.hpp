@@ -27,6 +27,8 @@
 //    run, the 18 deltas are wave-uniform and are fetched with scalar loads:
 //    no vector index load is issued at all (the GPU counterpart of the
 //    partial vectorization of Sect. 4.2).
+//  * Per-direction RIA: the same rule kept separately for each direction
+//    (IndexRIADir below), for lattices where the joint runs are short.
 #pragma once
 
 #include "d3q19.hpp"

@@ -1,7 +1,8 @@
 // Device solver and bandwidth micro-benchmarks behind the C ABI of
 // include/lbm_sparse.h: initialisation, time stepping (AA or OS-NT, with
-// adjacency list or RIA wave tables), macroscopic moments with deterministic
-// FP64 reductions, and PDF export / import in natural order.
+// adjacency list, RIA wave tables or per-direction RIA tables), macroscopic
+// moments with deterministic FP64 reductions, and PDF export / import in
+// natural order.
 
 #include <hip/hip_runtime.h>
 
