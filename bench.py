@@ -55,12 +55,41 @@ ODD_KERNEL = {"adjacency": "aa_odd<double, IndexIA, false>", "runs": "aa_odd<dou
               "direction": "aa_odd<double, IndexRIADir, false>"}
 
 
-def source_digest():
-    h = hashlib.sha256()
+def _strip_comments(text):
+    """C/C++ source without comments and blank-line or indentation changes."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif text[i] == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(text[i])
+            i += 1
+    lines = (" ".join(l.split()) for l in "".join(out).splitlines())
+    return "\n".join(l for l in lines if l)
+
+
+def source_digest(read=None):
+    """Digest of the kernel sources (comments and layout ignored), so that
+    counter results are only reused for the code they were taken on."""
     csrc = os.path.join(ROOT, "paper_1410_0412_amd", "csrc")
+    h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode() + fh.read())
+        if read is None:
+            with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+                text = fh.read()
+        else:
+            text = read(name)
+        h.update(name.encode() + _strip_comments(text).encode())
     return h.hexdigest()[:16]
 
 
