@@ -333,10 +333,13 @@ def precision_study(torch, args):
         if ref is None:
             ref = (rho, u)
         else:
-            du = torch.sqrt(((u - ref[1]) ** 2).sum(0)).max() / torch.sqrt((ref[1] ** 2).sum(0)).max()
+            scale = torch.sqrt((ref[1] ** 2).sum(0)).max()
+            du = torch.sqrt(((u - ref[1]) ** 2).sum(0)).max() / scale
             row.update({"u_normwise_rel_err_vs_f64": du.item(),
-                        "rho_max_abs_err_vs_f64": (rho - ref[0]).abs().max().item(),
-                        "ux_max_rel_err_vs_f64": ((u[0] - ref[1][0]).abs().max() / ref[1][0].abs().max()).item()})
+                        "rho_max_abs_err_vs_f64": (rho - ref[0]).abs().max().item()})
+            # per component: max |u_a - u_a,f64| over nodes, relative to max |u_f64|
+            for a, name in enumerate(("ux", "uy", "uz")):
+                row[name + "_max_err_rel_to_umax_vs_f64"] = ((u[a] - ref[1][a]).abs().max() / scale).item()
         row["u_max"] = u.abs().max().item()
         res[prec] = row
         log(prec, row)
