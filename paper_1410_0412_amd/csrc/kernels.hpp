@@ -37,13 +37,18 @@ namespace lbm {
 
 constexpr int kBlock = 256;
 
-// Workgroups are dispatched round-robin over the 8 XCDs of the chip; with
-// remapping, each XCD sweeps one contiguous range of tiles, so the partial
-// cache lines shared by neighbouring tiles stay in that XCD's L2.
-__device__ __forceinline__ int64_t tile_index(int remap) {
-  if (!remap) return blockIdx.x;
-  const int64_t per = gridDim.x >> 3;
-  return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, so in
+// plain order neighbouring tiles run on different XCDs and the cache lines
+// they share (partial lines of the scattered stores, gathered lines) meet in
+// no common L2. With a chunk of K > 0 workgroups, XCD x (= b mod 8) takes
+// chunks of K consecutive workgroup tiles in turn: x, x + 8, x + 16, ... .
+// Neighbouring tiles then share an L2, while the 8 XCDs still sweep one
+// region of memory together. The grid must be a multiple of 8K (the extra
+// workgroups find no nodes and return).
+__device__ __forceinline__ int64_t tile_index(int chunk) {
+  if (chunk <= 0) return blockIdx.x;
+  const int64_t k = chunk, x = blockIdx.x & 7, seq = blockIdx.x >> 3;
+  return ((seq / k) * 8 + x) * k + seq % k;
 }
 
 // ---------------------------------------------------------------- indices --
@@ -160,8 +165,8 @@ __device__ __forceinline__ int32_t pull_slot(int q, int32_t n, const int32_t (&a
 
 template <class S, bool TRT>
 __global__ void __launch_bounds__(kBlock)
-aa_even(S* __restrict__ F, int32_t N, Collision c, int remap) {
-  const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
+aa_even(S* __restrict__ F, int32_t N, Collision c, int chunk) {
+  const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   S* Fn = F + node_base(n);
@@ -175,8 +180,8 @@ aa_even(S* __restrict__ F, int32_t N, Collision c, int remap) {
 
 template <class S, class Idx, bool TRT>
 __global__ void __launch_bounds__(kBlock)
-aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int remap) {
-  const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
+aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int chunk) {
+  const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t a[18];
@@ -195,8 +200,8 @@ aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int remap) {
 
 template <class S, class Idx, bool TRT>
 __global__ void __launch_bounds__(kBlock)
-osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, Idx idx, Collision c, int remap) {
-  const int64_t n64 = tile_index(remap) * kBlock + threadIdx.x;
+osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, Idx idx, Collision c, int chunk) {
+  const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t a[18];

@@ -25,7 +25,7 @@ struct lbm_solver {
   hipStream_t stream = nullptr;
   int64_t t = 0;
   int cur = 0;     // OS-NT: grid that holds f*(t-1)
-  int remap = 1;   // XCD-aware tile order
+  bool remap = true;  // XCD-aware tile order for the indirect steps
   bool trt = false;
   Collision c;
 };
@@ -321,10 +321,22 @@ void dispatch(const lbm_solver* s, void* grid, Fn&& fn) {
   }
 }
 
+// Chunks of the XCD-aware tile order (workgroups of 256 nodes), measured on
+// the sphere pack, the foam and the channel: 32-64 for the AA odd step,
+// 16 for OS-NT; smaller chunks split neighbours, larger ones spread the XCDs
+// over distant regions of memory.
+constexpr int kOddChunk = 64;
+constexpr int kPullChunk = 16;
+
+// Grid of a launch in chunked tile order: a multiple of 8 * chunk.
+inline unsigned chunked_grid(unsigned tiles, int chunk) {
+  const unsigned m = 8u * (unsigned)chunk;
+  return chunk > 0 ? (tiles + m - 1) / m * m : tiles;
+}
+
 template <bool TRT>
 void launch_step_op(lbm_solver* s, int32_t N) {
   const unsigned tiles = grid_for(N);
-  const unsigned tiles8 = (tiles + 7) / 8 * 8;
   const dim3 b(kBlock);
   if (s->p.pattern == LBM_PATTERN_AA) {
     if (s->t % 2 == 0) {
@@ -335,20 +347,21 @@ void launch_step_op(lbm_solver* s, int32_t N) {
     } else {
       // the scattered stores of the odd step share partial lines between
       // neighbouring tiles: keep neighbours on one XCD
-      const int remap = s->remap;
+      const int chunk = s->remap ? kOddChunk : 0;
       dispatch(s, s->b.pdf[0], [&](auto* F, auto idx) {
         using S = std::remove_pointer_t<decltype(F)>;
-        hipLaunchKernelGGL((aa_odd<S, decltype(idx), TRT>), dim3(remap ? tiles8 : tiles), b, 0, s->stream,
-                           F, N, idx, s->c, remap);
+        hipLaunchKernelGGL((aa_odd<S, decltype(idx), TRT>), dim3(chunked_grid(tiles, chunk)), b, 0, s->stream,
+                           F, N, idx, s->c, chunk);
       });
     }
   } else {
     void* G = s->b.pdf[s->cur];
     void* H = s->b.pdf[1 - s->cur];
+    const int chunk = s->remap ? kPullChunk : 0;
     dispatch(s, G, [&](auto* Gt, auto idx) {
       using S = std::remove_pointer_t<decltype(Gt)>;
-      hipLaunchKernelGGL((osnt<S, decltype(idx), TRT>), dim3(tiles), b, 0, s->stream, (const S*)Gt, (S*)H, N,
-                         idx, s->c, 0);
+      hipLaunchKernelGGL((osnt<S, decltype(idx), TRT>), dim3(chunked_grid(tiles, chunk)), b, 0, s->stream,
+                         (const S*)Gt, (S*)H, N, idx, s->c, chunk);
     });
   }
 }
@@ -457,7 +470,7 @@ int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace
   s->ws = (double*)workspace;
   s->ws_bytes = workspace_bytes;
   s->stream = (hipStream_t)hip_stream;
-  s->remap = (p->flags & LBM_FLAG_NO_XCD_REMAP) ? 0 : 1;
+  s->remap = (p->flags & LBM_FLAG_NO_XCD_REMAP) == 0;
   Collision& c = s->c;
   s->trt = p->collision == LBM_TRT;
   c.omega = 1.0 / p->tau;
