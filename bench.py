@@ -300,6 +300,18 @@ def order_sweep(torch, args):
                             "odd_us": round(float(np.mean(d_o)) * 1e6, 1),
                             "loop_balance_B_per_FLUP": round(bl, 2),
                             "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4)}
+        if args.with_ia_osnt:
+            # FP64 AA-IA and OS-NT with each index source (the Sect. 5.1 RIA comparison)
+            for pattern, ria in (("aa", False), ("osnt", False), ("osnt", "runs"), ("osnt", "direction")):
+                wall, _, _, index = time_variant(torch, lat, p, pattern, ria, "f64", args.steps, args.warmup)
+                mflups = 2 * N * args.steps / wall / 1e6
+                if pattern == "aa":
+                    bl = (kernel_bytes("even", N, ib[index]) + kernel_bytes("odd", N, ib[index])) / 2 / N
+                else:
+                    bl = kernel_bytes("osnt", N, ib[index]) / N
+                row["%s_%s_f64" % (pattern, index)] = {
+                    "mflups": round(mflups, 1), "loop_balance_B_per_FLUP": round(bl, 2),
+                    "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4)}
         log(spec, row)
         out["orders"][spec] = row
         del lat
@@ -397,6 +409,8 @@ def main():
                     help="named synthetic workload (default: the 512x128x128 sphere pack)")
     ap.add_argument("--orders", default=None,
                     help="enumeration sweep instead of the default line, e.g. lex:0,lex:8,morton,hilbert")
+    ap.add_argument("--with-ia-osnt", action="store_true",
+                    help="with --orders: also time FP64 AA-IA and OS-NT with every index source")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
