@@ -60,9 +60,9 @@ enum { LBM_BGK = 0, LBM_TRT = 1 };
 /* Neighbour index source of a solver (lbm_params.ria): the adjacency list,
  * the paper's runs (Sect. 4.1) or per-direction runs. */
 enum { LBM_INDEX_ADJ = 0, LBM_INDEX_RUNS = 1, LBM_INDEX_DIRECTION_RUNS = 2 };
-/* Solver flag: launch the AA odd step and OS-NT in plain tile order. By
- * default each XCD takes chunks of consecutive 256-node tiles in turn, so
- * neighbouring tiles share an L2. */
+/* Solver flag: launch the step kernels in plain tile order. By default each
+ * XCD takes chunks of consecutive 256-node tiles in turn, so neighbouring
+ * tiles share an L2. */
 enum { LBM_FLAG_NO_XCD_REMAP = 1 };
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -86,8 +86,8 @@ class Solver:
                paper's operator) with that magic parameter.
     pbb        True: allocate a per-node partial-bounce-back solid fraction
                (``solid_frac``, zero-initialised; AA, FP64, BGK only).
-    xcd_remap  AA odd step and OS-NT: each XCD takes chunks of consecutive
-               tiles in turn (False: plain tile order).
+    xcd_remap  step kernels: each XCD takes chunks of consecutive tiles in
+               turn (False: plain tile order).
     """
 
     def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria=True,
