@@ -65,8 +65,9 @@ def test_spherepack_variants_identical_and_conserve_mass(pack):
         assert np.array_equal(r, results[0])
 
 
-@pytest.mark.parametrize("order,block", [("lex", 0), ("morton", 0), ("hilbert_ls", 8)])
-def test_foam384_sampled_sites(order, block):
+@pytest.mark.parametrize("order,block,ria", [("lex", 0, True), ("lex", 8, "direction"), ("morton", 0, True),
+                                             ("hilbert_ls", 8, True)])
+def test_foam384_sampled_sites(order, block, ria):
     # the 384^3 foam of the enumeration sweep and the precision study
     mask, p = workload("foam-384", seed=0)
     steps = 2
@@ -75,8 +76,8 @@ def test_foam384_sampled_sites(order, block):
     pick = fl[np.random.default_rng(22).choice(len(fl), 24, replace=False)]
     sites = np.stack(np.unravel_index(pick, mask.shape), 1)
     want = dense.cone_sites(mask.astype(bool), p["periodic"], p["tau"], p["force"], steps, rho0, u0, sites)
-    print("case foam-384 sampled", order, block, flush=True)
-    lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], "aa", True, order, block)
+    print("case foam-384 sampled", order, block, ria, flush=True)
+    lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], "aa", ria, order, block)
     r, v = node_fields(lat, rho0, u0)
     del rho0, u0
     s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
