@@ -414,6 +414,8 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
+    ap.add_argument("--micro-sizes", default=None,
+                    help="micro-benchmarks only, at these node counts (comma separated), one JSON line")
     ap.add_argument("--stride-sweep", action="store_true",
                     help="U-19A bandwidth against the padding of the stream stride")
     ap.add_argument("--precision-study", action="store_true",
@@ -442,6 +444,14 @@ def main():
         return precision_study(torch, args)
     if args.stride_sweep:
         return stride_sweep(torch, args)
+    if args.micro_sizes:
+        rows = {}
+        for n in (int(x) for x in args.micro_sizes.split(",")):
+            rows[n] = microbench(torch, n)
+            log(n, rows[n])
+        print(json.dumps({"metric": "micro-benchmark GB/s vs node count (2 * 19 * 8 B per node; copy: 2 * 19 * ld * 8 B)",
+                          "n_gpus": 1, "data": "synthetic", "sizes": rows}), flush=True)
+        return
     if args.workload != WORKLOAD:
         print("the default line is defined on %s; use --orders for other workloads" % WORKLOAD, file=sys.stderr)
         sys.exit(2)
