@@ -26,6 +26,8 @@ struct lbm_solver {
   int64_t t = 0;
   int cur = 0;     // OS-NT: grid that holds f*(t-1)
   bool remap = true;  // XCD-aware tile order for the indirect steps
+  bool lds_ready = false;  // occupancy reservations below computed
+  unsigned even_lds = 0, pull_lds = 0;  // LDS bytes reserved per workgroup
   bool trt = false;
   Collision c;
 };
@@ -331,6 +333,38 @@ constexpr int kOddChunk = 64;
 constexpr int kEvenChunk = 64;
 constexpr int kPullChunk = 16;
 
+// Occupancy caps (workgroups per CU; 0 = as many as the registers allow),
+// measured per storage precision. The streaming even step in FP64 and FP32
+// runs fastest with 2 workgroups (8 waves) per CU: fewer requests in flight
+// keep the DRAM accesses in order (FP64: -2 % of its time on the sphere pack,
+// -8 % on the 384^3 foam; FP32 on the foam: -13 %). In FP16 a wave moves a
+// quarter of the bytes and the cap costs 25 %. OS-NT in FP64 runs best with
+// 5. The odd step needs all the concurrency it gets for its gathers. The cap
+// is an LDS reservation in the launch; the kernels use no LDS.
+constexpr int kEvenWgsPerCu[3] = {2, 2, 0};  // LBM_F64, LBM_F32, LBM_F16
+constexpr int kPullWgsPerCu[3] = {5, 0, 0};
+
+// LDS bytes per workgroup that allow exactly `wgs` workgroups per CU, or 0
+// (no cap) if the device limits cannot express it.
+unsigned lds_for(int per_cu, int per_block, int wgs) {
+  if (per_cu <= 0 || per_block <= 0 || wgs <= 0) return 0;
+  const int bytes = std::min(per_cu / wgs, per_block);
+  return (bytes > 0 && per_cu / bytes == wgs) ? (unsigned)bytes : 0;
+}
+
+void init_occupancy(lbm_solver* s) {
+  int dev = 0, per_cu = 0, per_block = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    per_cu = per_block = 0;  // no caps
+  }
+  const int k = s->p.precision;  // validated: LBM_F64, LBM_F32 or LBM_F16
+  s->even_lds = lds_for(per_cu, per_block, kEvenWgsPerCu[k]);
+  s->pull_lds = lds_for(per_cu, per_block, kPullWgsPerCu[k]);
+  s->lds_ready = true;
+}
+
 // Grid of a launch in chunked tile order: a multiple of 8 * chunk.
 inline unsigned chunked_grid(unsigned tiles, int chunk) {
   const unsigned m = 8u * (unsigned)chunk;
@@ -341,13 +375,14 @@ template <bool TRT>
 void launch_step_op(lbm_solver* s, int32_t N) {
   const unsigned tiles = grid_for(N);
   const dim3 b(kBlock);
+  if (!s->lds_ready) init_occupancy(s);
   if (s->p.pattern == LBM_PATTERN_AA) {
     if (s->t % 2 == 0) {
       dispatch(s, s->b.pdf[0], [&](auto* F, auto) {
         using S = std::remove_pointer_t<decltype(F)>;
         const int chunk = s->remap ? kEvenChunk : 0;
-        hipLaunchKernelGGL((aa_even<S, TRT>), dim3(chunked_grid(tiles, chunk)), b, 0, s->stream, F, N, s->c,
-                           chunk);
+        hipLaunchKernelGGL((aa_even<S, TRT>), dim3(chunked_grid(tiles, chunk)), b, s->even_lds, s->stream, F,
+                           N, s->c, chunk);
       });
     } else {
       // the scattered stores of the odd step share partial lines between
@@ -365,8 +400,8 @@ void launch_step_op(lbm_solver* s, int32_t N) {
     const int chunk = s->remap ? kPullChunk : 0;
     dispatch(s, G, [&](auto* Gt, auto idx) {
       using S = std::remove_pointer_t<decltype(Gt)>;
-      hipLaunchKernelGGL((osnt<S, decltype(idx), TRT>), dim3(chunked_grid(tiles, chunk)), b, 0, s->stream,
-                         (const S*)Gt, (S*)H, N, idx, s->c, chunk);
+      hipLaunchKernelGGL((osnt<S, decltype(idx), TRT>), dim3(chunked_grid(tiles, chunk)), b, s->pull_lds,
+                         s->stream, (const S*)Gt, (S*)H, N, idx, s->c, chunk);
     });
   }
 }
