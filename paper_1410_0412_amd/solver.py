@@ -75,10 +75,10 @@ class Solver:
     """D3Q19 BGK solver on a :class:`Lattice`.
 
     pattern    "aa" (one grid) or "osnt" (two grids, pull).
-    ria        Neighbour index source. True or "runs": the paper's RIA runs
+    ria        Neighbour index source. "auto" (default): the choice of
+               :func:`choose_index`; True or "runs": the paper's RIA runs
                (Sect. 4.1) as per-wavefront tables; False or "adjacency": the
-               adjacency list; "direction": per-direction runs; "auto": the
-               choice of :func:`choose_index`.
+               adjacency list; "direction": per-direction runs.
     precision  "f64" (FP64 storage and arithmetic), "f32" or "f16"
                (storage of deviations from the rest state, FP32 arithmetic).
     f16_scale_log2  FP16 storage holds d_q * 2^s / w_q (default s = 10).
@@ -90,7 +90,7 @@ class Solver:
                turn (False: plain tile order).
     """
 
-    def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria=True,
+    def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria="auto",
                  precision="f64", rho0=1.0, device=None, xcd_remap=True, f16_scale_log2=10,
                  trt_magic=None, pbb=False):
         import torch
