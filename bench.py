@@ -364,6 +364,87 @@ def precision_study(torch, args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_bench(torch, args):
+    """Differentiation extension on the 128^3 sphere pack: the forward PBB
+    step, the adjoint step and one whole gradient of the outlet flux (T
+    steps, checkpoints every 20), with their algorithmic bytes."""
+    from lbm_inputs import workload, pbb_fraction
+    from paper_1410_0412_amd import Lattice, Solver, outlet_flux
+
+    name = "spherepack-128"
+    mask, p = workload(name, seed=args.seed)
+    lat = Lattice(mask, p["periodic"], p["order"], p["block"])
+    N, T, every = lat.n_fluid, p["steps"], 20
+    nv = lat.node_voxel().astype(np.int64)
+    ns = torch.from_numpy(pbb_fraction(mask, seed=1).reshape(-1)[nv]).cuda()
+    wv = np.zeros(mask.shape)
+    wv[-1] = 1.0
+    w = torch.from_numpy(wv.reshape(-1)[nv]).cuda()
+    s = Solver(lat, p["tau"], p["force"], pattern="aa", ria="auto", pbb=True)
+    ib = lat.index_bytes()[s.index]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    # forward PBB steps
+    s.set_solid_fraction(ns)
+    s.init()
+    s.step(2 * args.warmup)
+    e0, e1 = ev(), ev()
+    e0.record()
+    s.step(T)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_s = e0.elapsed_time(e1) * 1e-3 / T
+    # adjoint steps over stored states of one checkpoint segment
+    states = []
+    s.init()
+    for _ in range(every):
+        states.append(s.pdf[0].clone())
+        s.step(1)
+    lam = torch.empty_like(s.pdf[0])
+    grad = torch.zeros(N, dtype=torch.float64, device="cuda")
+    s.adjoint_seed(w, 0, every, lam)
+    for t in range(every - 1, -1, -1):  # warm-up pass
+        s.adjoint_step(states[t], t, lam, grad)
+    s.adjoint_seed(w, 0, every, lam)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    for t in range(every - 1, -1, -1):
+        s.adjoint_step(states[t], t, lam, grad)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_s = e0.elapsed_time(e1) * 1e-3 / every
+    del states
+    # one whole gradient: forward with checkpoints, recomputation, adjoint
+    x = ns.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = outlet_flux(x, s, T, every, w)
+    J.backward()
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t0
+    # algorithmic bytes per node: PBB forward reads and writes 19 PDFs and
+    # reads ns; the adjoint reads the forward state and lambda, writes lambda,
+    # reads ns and updates the gradient; odd steps add the index bytes
+    fwd_b = 38 * 8 + 8 + ib / 2
+    adj_b = 57 * 8 + 8 + 16 + ib / 2
+    out = {"metric": "adjoint AA step (PBB, FP64): MFLUP/s and % of HBM roofline", "n_gpus": 1,
+           "data": "synthetic", "unit": "MFLUP/s",
+           "config": {"workload": name, "fluid_nodes": N, "steps": T, "checkpoint_every": every, "index": s.index,
+                      "tau": p["tau"], "force": list(p["force"])},
+           "forward_pbb": {"mflups": round(N / fwd_s / 1e6, 1), "us_per_step": round(fwd_s * 1e6, 2),
+                           "B_per_FLUP": round(fwd_b, 2),
+                           "frac_of_hbm_roofline": round(N / fwd_s * fwd_b / (HBM_PEAK_GBS * 1e9), 4)},
+           "adjoint": {"mflups": round(N / adj_s / 1e6, 1), "us_per_step": round(adj_s * 1e6, 2),
+                       "B_per_FLUP": round(adj_b, 2),
+                       "frac_of_hbm_roofline": round(N / adj_s * adj_b / (HBM_PEAK_GBS * 1e9), 4)},
+           "gradient": {"seconds": round(grad_s, 4), "J": J.item(),
+                        "forward_step_equivalents": round(grad_s / fwd_s / T, 2),
+                        "note": "forward with checkpoints + recomputation of every segment + adjoint, "
+                                "wall clock including host-side launch and checkpoint copies"}}
+    log(out)
+    print(json.dumps(out), flush=True)
+
+
 def stride_sweep(torch, args):
     """U-19A (19-stream in-place update, the AA even-step traffic) for stream
     strides padded by different amounts: the effect of the paper's padding
@@ -414,6 +495,8 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the forward PBB step, the adjoint step and one gradient on the 128^3 sphere pack")
     ap.add_argument("--micro-sizes", default=None,
                     help="micro-benchmarks only, at these node counts (comma separated), one JSON line")
     ap.add_argument("--stride-sweep", action="store_true",
@@ -444,6 +527,8 @@ def main():
         return precision_study(torch, args)
     if args.stride_sweep:
         return stride_sweep(torch, args)
+    if args.adjoint:
+        return adjoint_bench(torch, args)
     if args.micro_sizes:
         rows = {}
         for n in (int(x) for x in args.micro_sizes.split(",")):
