@@ -39,8 +39,8 @@ __device__ __forceinline__ void step_slots(int32_t n, const Idx& idx, int32_t (&
 template <class Idx, bool ODD>
 __global__ void __launch_bounds__(kBlock)
 aa_step_pbb(double* __restrict__ F, int32_t N, Idx idx, Collision c,
-            const double* __restrict__ ns) {
-  const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+            const double* __restrict__ ns, int chunk) {
+  const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t g[Q];
@@ -57,8 +57,8 @@ aa_step_pbb(double* __restrict__ F, int32_t N, Idx idx, Collision c,
 template <class Idx, bool ODD>
 __global__ void __launch_bounds__(kBlock)
 aa_adjoint(const double* __restrict__ F, double* __restrict__ Lam, int32_t N, Idx idx,
-           Collision c, const double* __restrict__ ns, double* __restrict__ grad) {
-  const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+           Collision c, const double* __restrict__ ns, double* __restrict__ grad, int chunk) {
+  const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t g[Q];

@@ -408,14 +408,17 @@ void launch_step_op(lbm_solver* s, int32_t N) {
 
 void launch_step_pbb(lbm_solver* s, int32_t N) {
   double* F = (double*)s->b.pdf[0];
+  // the odd step's tile order (the even step of the PBB path shares it)
+  const int chunk = s->remap ? kOddChunk : 0;
+  const dim3 grid(chunked_grid(grid_for(N), chunk));
   auto go = [&](auto idx) {
     using I = decltype(idx);
     if (s->t % 2 == 0)
-      hipLaunchKernelGGL((aa_step_pbb<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N,
-                         idx, s->c, s->b.solid_frac);
+      hipLaunchKernelGGL((aa_step_pbb<I, false>), grid, dim3(kBlock), 0, s->stream, F, N, idx, s->c,
+                         s->b.solid_frac, chunk);
     else
-      hipLaunchKernelGGL((aa_step_pbb<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, F, N,
-                         idx, s->c, s->b.solid_frac);
+      hipLaunchKernelGGL((aa_step_pbb<I, true>), grid, dim3(kBlock), 0, s->stream, F, N, idx, s->c,
+                         s->b.solid_frac, chunk);
   };
   with_index(s, go);
 }
@@ -698,14 +701,16 @@ int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, d
   if (rc) return rc;
   const int32_t N = (int32_t)s->p.n_fluid;
   if (N == 0) return LBM_OK;
+  const int chunk = s->remap ? kOddChunk : 0;
+  const dim3 grid(chunked_grid(grid_for(N), chunk));
   auto go = [&](auto idx) {
     using I = decltype(idx);
     if (t % 2 == 0)
-      hipLaunchKernelGGL((aa_adjoint<I, false>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, fwd, lam, N,
-                         idx, s->c, s->b.solid_frac, grad);
+      hipLaunchKernelGGL((aa_adjoint<I, false>), grid, dim3(kBlock), 0, s->stream, fwd, lam, N, idx, s->c,
+                         s->b.solid_frac, grad, chunk);
     else
-      hipLaunchKernelGGL((aa_adjoint<I, true>), dim3(grid_for(N)), dim3(kBlock), 0, s->stream, fwd, lam, N,
-                         idx, s->c, s->b.solid_frac, grad);
+      hipLaunchKernelGGL((aa_adjoint<I, true>), grid, dim3(kBlock), 0, s->stream, fwd, lam, N, idx, s->c,
+                         s->b.solid_frac, grad, chunk);
   };
   with_index(s, go);
   return device_status("adjoint_step");
