@@ -100,8 +100,11 @@ struct IndexRIA {
 // On fragmented porous media a node then rarely needs fresh deltas for all 18
 // directions: the tables hold 4 B per direction run plus 12 B per wave and
 // direction, against 72 B per run of the joint encoding. Wave w reads its 18
-// head words and 18 bases as wave-uniform values; a direction whose run spans
-// the whole wave fetches its delta with a scalar load.
+// head words and 18 bases as wave-uniform values. Every lane then finds its
+// run per direction with a popcount, and the 18 delta loads go out together;
+// a direction whose run spans the whole wave reads one address in all lanes
+// (one cache line). This encoding is chosen for fragmented lattices, where
+// such directions are rare, so it keeps no scalar-load branch per direction.
 struct IndexRIADir {
   const int32_t* __restrict__ delta;       // [RD]
   const uint64_t* __restrict__ head_bits;  // [W][18]
@@ -113,17 +116,11 @@ struct IndexRIADir {
     const int32_t* rw = run_base + w * 18;
     const int lane = n & 63;
     const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    int32_t d[18];
 #pragma unroll
-    for (int q = 0; q < 18; ++q) {
-      const uint64_t bits = bw[q];
-      int32_t d;
-      if ((bits >> 1) == 0) {
-        d = delta[__builtin_amdgcn_readfirstlane(rw[q] + (int32_t)(bits & 1))];
-      } else {
-        d = delta[rw[q] + __popcll(bits & upto)];
-      }
-      a[q] = d == INT32_MIN ? -1 : n + d;
-    }
+    for (int q = 0; q < 18; ++q) d[q] = delta[rw[q] + __popcll(bw[q] & upto)];
+#pragma unroll
+    for (int q = 0; q < 18; ++q) a[q] = d[q] == INT32_MIN ? -1 : n + d[q];
   }
 };
 

@@ -39,15 +39,15 @@ def aligned_empty(torch, numel, dtype, device, align=_GRID_ALIGN):
     return base[off:off + numel]
 
 
-def choose_index(lattice, pattern="aa", precision="f64", margin=0.02, ratio=0.7):
-    """Index source for ``ria="auto"``: per-direction runs when they save at
-    least ``margin`` of the loop balance (bytes per FLUP with the paper's
-    runs) and need at most ``ratio`` times the paper's index bytes; else the
-    paper's runs. The AA pattern pays the index in every second step, OS-NT
-    in every step. The ratio bound keeps the paper's runs where runs are short
-    in every direction (space-filling curves): there per-direction deltas are
-    read without sharing between lanes and their decode costs more than the
-    few bytes it saves."""
+def choose_index(lattice, pattern="aa", precision="f64", margin=0.0, ratio=0.7):
+    """Index source for ``ria="auto"``: per-direction runs when they need at
+    most ``ratio`` times the index bytes of the paper's runs (and save more
+    than ``margin`` of the loop balance, the bytes per FLUP with the paper's
+    runs); else the paper's runs. The AA pattern pays the index in every
+    second step, OS-NT in every step. The ratio bound keeps the paper's runs
+    where runs are short in every direction (space-filling curves): there
+    per-direction deltas are read without sharing between lanes and save too
+    few bytes to pay for the extra table reads."""
     try:
         b = lattice.index_bytes()
     except _capi.LbmError:  # per-direction run count exceeds the int32 table index
@@ -55,7 +55,7 @@ def choose_index(lattice, pattern="aa", precision="f64", margin=0.02, ratio=0.7)
     s = {"f64": 8, "f32": 4, "f16": 2}[precision]
     share = 0.5 if pattern == "aa" else 1.0
     balance = 38.0 * s + share * b["runs"]
-    saves = share * (b["runs"] - b["direction"]) >= margin * balance
+    saves = share * (b["runs"] - b["direction"]) > margin * balance
     return "direction" if saves and b["direction"] <= ratio * b["runs"] else "runs"
 
 

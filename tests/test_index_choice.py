@@ -14,15 +14,15 @@ class FakeLattice:
 
 
 @pytest.mark.parametrize("runs,direction,pattern,precision,want", [
-    (48.5, 18.1, "aa", "f64", "direction"),    # fragmented sphere pack: saves 4.6 % of 328 B/FLUP
+    (48.5, 18.1, "aa", "f64", "direction"),    # fragmented sphere pack: 0.37 of the bytes
     (48.5, 18.1, "osnt", "f64", "direction"),
     (2.4, 4.2, "aa", "f64", "runs"),           # channel: per-direction tables are larger
-    (9.9, 5.9, "aa", "f64", "runs"),           # long runs: saves 0.6 %, below the margin
-    (9.9, 5.9, "aa", "f32", "runs"),           # 2.0 of 157 B/FLUP: 1.3 %
-    (9.9, 5.9, "aa", "f16", "direction"),      # 2.0 of 81 B/FLUP: 2.5 %
-    (33.0, 16.2, "aa", "f64", "direction"),    # LS B=8 on the foam: 2.6 %
-    (72.2, 57.2, "aa", "f64", "runs"),         # Morton: saves 2.2 %, but 0.79 of the bytes
-    (72.2, 63.6, "aa", "f32", "runs"),         # Hilbert
+    (9.9, 5.9, "aa", "f64", "direction"),      # LS foam: 0.60 of the bytes
+    (9.9, 5.9, "aa", "f16", "direction"),
+    (33.0, 16.2, "aa", "f64", "direction"),    # LS B=8 on the foam
+    (72.2, 57.2, "aa", "f64", "runs"),         # Morton: 0.79 of the bytes
+    (72.2, 63.6, "aa", "f32", "runs"),         # Hilbert: 0.88
+    (10.0, 10.0, "aa", "f64", "runs"),         # no saving
 ])
 def test_choice(runs, direction, pattern, precision, want):
     assert solver.choose_index(FakeLattice(runs, direction), pattern, precision) == want
