@@ -40,8 +40,9 @@ constexpr int kBlock = 256;
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, so in
 // plain order neighbouring tiles run on different XCDs and the cache lines
 // they share (partial lines of the scattered stores, gathered lines) meet in
-// no common L2. With a chunk of K > 0 workgroups, XCD x (= b mod 8) takes
-// chunks of K consecutive workgroup tiles in turn: x, x + 8, x + 16, ... .
+// no common L2. With chunks of K > 0 workgroup tiles (256 nodes each), the
+// tiles are cut into chunks of K consecutive tiles, and XCD x (the XCD of
+// workgroup b is b mod 8) takes chunks x, x + 8, x + 16, ... in turn.
 // Neighbouring tiles then share an L2, while the 8 XCDs still sweep one
 // region of memory together. The grid must be a multiple of 8K (the extra
 // workgroups find no nodes and return).
@@ -103,8 +104,8 @@ struct IndexRIA {
 // head words and 18 bases as wave-uniform values. Every lane then finds its
 // run per direction with a popcount, and the 18 delta loads go out together;
 // a direction whose run spans the whole wave reads one address in all lanes
-// (one cache line). This encoding is chosen for fragmented lattices, where
-// such directions are rare, so it keeps no scalar-load branch per direction.
+// (one cache line). A scalar-load branch per direction for such directions
+// measured slower: it serialises the loads of a wave.
 struct IndexRIADir {
   const int32_t* __restrict__ delta;       // [RD]
   const uint64_t* __restrict__ head_bits;  // [W][18]
