@@ -1,7 +1,9 @@
 """Parity at the benchmark sizes, in the launch configuration the benchmark
 times: sampled sites against the oracle's dependency-cone evaluation after a
-few steps, and properties that hold at any size (bitwise identity of all four
-propagation variants, mass conservation over many steps)."""
+few steps, properties that hold at any size (bitwise identity of all
+propagation variants, mass conservation over many steps), deviation storage
+against the FP64 path, and the largest lattice the 32-bit slot offsets
+allow."""
 import numpy as np
 import pytest
 
@@ -87,4 +89,61 @@ def test_foam384_sampled_sites(order, block, ria):
     node_of[lat.node_voxel().astype(np.int64)] = np.arange(lat.n_fluid)
     idx = torch.from_numpy(node_of[pick]).cuda()
     got = f[:, idx].T.cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("prec,tol_u,tol_rho", [("f32", 1e-5, 1e-7), ("f16", 5e-3, 5e-5)])
+def test_spherepack_deviation_storage_against_fp64(pack, prec, tol_u, tol_rho):
+    # deviation storage at the benchmark size against the FP64 path (which is
+    # bitwise the oracle), random state, 20 steps; bounds as for the small cases
+    mask, p = pack
+    steps = 20
+    rho0, u0 = init_fields(mask.shape, seed=31)
+    out = {}
+    for pr in ("f64", prec):
+        print("case spherepack deviation storage", pr, flush=True)
+        lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], "aa", "auto", p["order"], p["block"],
+                            precision=pr)
+        r, v = node_fields(lat, rho0, u0)
+        s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+        s.step(steps)
+        rho, u, tot = s.moments()
+        out[pr] = (rho.cpu().numpy(), u.cpu().numpy(), tot[0].item())
+        del s
+    (r64, u64, m64), (rl, ul, ml) = out["f64"], out[prec]
+    du = np.sqrt(((ul - u64) ** 2).sum(0)).max() / np.sqrt((u64 ** 2).sum(0)).max()
+    drho = np.abs(rl - r64).max()
+    print("%s: normwise u %.3e, max rho %.3e, mass %.3e" % (prec, du, drho, abs(ml - m64) / m64), flush=True)
+    assert du <= tol_u and drho <= tol_rho and abs(ml - m64) / m64 <= 1e-6
+
+
+def test_maximum_size_lattice():
+    # the largest lattice the 32-bit slot offsets allow: a fully fluid
+    # periodic 480 x 480 x 490 box, N = 112,896,000 nodes, 19 * ldf just
+    # below 2^31 - 1; sampled sites (including the last node) after 3 steps
+    # against the oracle's dependency cone, bitwise
+    shape = (480, 480, 490)
+    per = (True, True, True)
+    tau, force, steps = 0.7, (1e-6, 0.0, 0.0), 3
+    mask = np.zeros(shape, np.uint8)
+    print("case maximum size: building the lattice", flush=True)
+    from paper_1410_0412_amd import Lattice, Solver
+    lat = Lattice(mask, per, "lex", 0)
+    N = lat.n_fluid
+    assert N == 480 * 480 * 490 and 19 * ((N + 63) // 64 * 64) <= 2 ** 31 - 1
+    s = Solver(lat, tau, force, pattern="aa", ria="auto")
+    rho0, u0 = init_fields(shape, seed=41)
+    r, v = node_fields(lat, rho0, u0)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    del r, v
+    print("case maximum size: stepping, index", s.index, flush=True)
+    s.step(steps)
+    rng = np.random.default_rng(42)
+    sites = np.stack([rng.integers(0, n, 30) for n in shape], 1)
+    sites = np.concatenate([sites, [[479, 479, 489], [0, 0, 0]]])
+    want = dense.cone_sites(mask.astype(bool), per, tau, force, steps, rho0, u0, sites)
+    del rho0, u0
+    node = torch.from_numpy((sites[:, 0] * shape[1] + sites[:, 1]) * shape[2] + sites[:, 2]).cuda()
+    f = s.export_pdfs()
+    got = f[:, node].T.cpu().numpy()
     assert np.array_equal(got, want)
