@@ -147,3 +147,26 @@ def test_maximum_size_lattice():
     f = s.export_pdfs()
     got = f[:, node].T.cpu().numpy()
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("pattern", ["aa", "osnt"])
+def test_spherepack_trt_sampled_sites(pack, pattern):
+    # the paper's TRT collision (magic 3/16) at the benchmark size, bitwise
+    mask, p = pack
+    steps, magic = 3, 3.0 / 16.0
+    rho0, u0 = init_fields(mask.shape, seed=51)
+    fl = np.argwhere(mask == 0)
+    sites = fl[np.random.default_rng(52).choice(len(fl), 32, replace=False)]
+    want = dense.cone_sites(mask.astype(bool), p["periodic"], p["tau"], p["force"], steps, rho0, u0, sites,
+                            magic=magic)
+    print("case spherepack TRT sampled", pattern, flush=True)
+    lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], pattern, "auto", p["order"], p["block"],
+                        trt_magic=magic)
+    r, v = node_fields(lat, rho0, u0)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    s.step(steps)
+    f = s.export_pdfs().cpu().numpy()
+    node_of = np.full(mask.size, -1, np.int64)
+    node_of[lat.node_voxel().astype(np.int64)] = np.arange(lat.n_fluid)
+    vox = (sites[:, 0] * mask.shape[1] + sites[:, 1]) * mask.shape[2] + sites[:, 2]
+    assert np.array_equal(f[:, node_of[vox]].T, want)
