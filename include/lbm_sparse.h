@@ -224,8 +224,11 @@ int lbm_solver_workspace_bytes(const lbm_params* p, int64_t* bytes);
  * hipStream_t all work is queued on (NULL: the default stream). The solver
  * starts at t = 0 with undefined PDFs; call an init or import first.
  * Errors: LBM_EINVAL (tau <= 1/2, bad flags, missing buffers, ldf < N or not
- * a multiple of 64, lda < N, ldr < R), LBM_ERANGE (N >= 2^31 or a slot index
- * 19*ldf that does not fit 2^31 - 1 elements), LBM_ENOMEM.
+ * a multiple of 64, lda < N, ldr < R, per-direction tables with fewer than 18
+ * runs), LBM_ERANGE (N >= 2^31, a slot index 19*ldf that does not fit
+ * 2^31 - 1 elements, or more than 2^31 - 1 per-direction runs), LBM_ENOMEM.
+ * Creation touches no device; the device limits used by the launches are
+ * read at the first step.
  */
 int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace,
                       int64_t workspace_bytes, void* hip_stream, lbm_solver** out);
@@ -243,7 +246,9 @@ int lbm_solver_init_equilibrium(lbm_solver* s, const double* rho, const double* 
 /*
  * Advance n_steps time steps (one kernel launch per step, asynchronous).
  * AA: even t runs the direct step, odd t the indirect step (Sect. 4);
- * OS-NT: pull step into the other grid, then the grids swap.
+ * OS-NT: pull step into the other grid, then the grids swap. Workgroups take
+ * tiles in XCD-aware chunks (unless LBM_FLAG_NO_XCD_REMAP), and the
+ * streaming kernels reserve LDS they do not use, to cap their occupancy.
  */
 int lbm_solver_step(lbm_solver* s, int64_t n_steps);
 
