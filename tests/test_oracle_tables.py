@@ -75,6 +75,35 @@ def test_channel_matches_table2(channel_tables):
     assert round(100 * tables.simd_fraction(rs, 4)) == GOLD["channel"]["simd_percent"]
 
 
+def test_channel_direction_runs_by_hand(channel_tables):
+    # 500 x 100 x 100 channel, fluid y, z in 1..98, periodic x, LS (z
+    # fastest), pull entries at x - c_q. Counted by hand per direction:
+    # * c_z != 0, c_y = 0: the wall side of each z-line reads -1, so every
+    #   line has 2 heads (where the entries turn -1 and where they turn
+    #   fluid): 2 * 98 * 500.
+    # * c_z = 0, c_y != 0: the y-line next to the wall reads -1 in every
+    #   plane: 2 heads per plane.
+    # * only c_x: one offset per plane pair, broken once by the wrap: 2.
+    # * c_y and c_z both nonzero: per plane, the all-wall y-line adds one
+    #   head and each other y-line two, except where the all-wall line
+    #   continues a -1 run left by the previous line: 194 per plane; for
+    #   (0,+1,-1) and (0,-1,+1) the all-wall line follows a -1 entry of the
+    #   previous plane, so only node 0 adds a head there: 97,000 + 1.
+    _, _, adj, _ = channel_tables
+    heads = tables.direction_heads(adj).sum(axis=1)
+    for q in range(1, 19):
+        cx, cy, cz = C[q]
+        if cz and not cy:
+            want = 98_000
+        elif cy and not cz:
+            want = 1_000
+        elif not cy and not cz:
+            want = 2
+        else:
+            want = 97_001 if cy != cz else 97_000
+        assert heads[q - 1] == want, (q, heads[q - 1], want)
+
+
 def test_channel_blocking_100_equals_1():
     # Sect. 5.6: on the 100-wide channel, B = 1 and B = 100 give the same order
     mask = channel_mask(40, 100, 100)
