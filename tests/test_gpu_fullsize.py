@@ -92,6 +92,44 @@ def test_foam384_sampled_sites(order, block, ria):
     assert np.array_equal(got, want)
 
 
+def test_channel_sampled_sites_and_variants():
+    # the paper's empty 500x100x100 channel (Sect. 5.1), LS with B = 1: long
+    # runs in every direction, the case RIA was designed for
+    mask, p = workload("channel-500x100x100")
+    steps = 3
+    rho0, u0 = init_fields(mask.shape, seed=41)
+    fl = np.argwhere(mask == 0)
+    rng = np.random.default_rng(42)
+    wall = fl[(fl[:, 1] == 1) | (fl[:, 1] == 98) | (fl[:, 2] == 1) | (fl[:, 2] == 98)]
+    seam = fl[(fl[:, 0] == 0) | (fl[:, 0] == mask.shape[0] - 1)]
+    sites = np.concatenate([fl[rng.choice(len(fl), 24, replace=False)],
+                            wall[rng.choice(len(wall), 8, replace=False)],
+                            seam[rng.choice(len(seam), 4, replace=False)]])
+    want = dense.cone_sites(mask.astype(bool), p["periodic"], p["tau"], p["force"], steps, rho0, u0, sites)
+    vox = (sites[:, 0] * mask.shape[1] + sites[:, 1]) * mask.shape[2] + sites[:, 2]
+    first = None
+    for pattern, ria in VARIANTS:
+        print("case channel sampled", pattern, ria, flush=True)
+        lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], pattern, ria, p["order"], p["block"])
+        assert lat.n_fluid == 500 * 98 * 98
+        r, v = node_fields(lat, rho0, u0)
+        s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+        s.step(steps)
+        f = s.export_pdfs()
+        node_of = np.full(mask.size, -1, np.int64)
+        node_of[lat.node_voxel().astype(np.int64)] = np.arange(lat.n_fluid)
+        got = f[:, torch.from_numpy(node_of[vox]).cuda()].T.cpu().numpy()
+        assert np.array_equal(got, want), (pattern, ria)
+        # 16 more steps: t = 19 is odd, so AA exports through its odd-step slots
+        s.step(16)
+        g = s.export_pdfs()
+        if first is None:
+            first = g
+        else:
+            assert torch.equal(g, first), (pattern, ria)
+        del s, f, g
+
+
 @pytest.mark.parametrize("prec,tol_u,tol_rho", [("f32", 1e-5, 1e-7), ("f16", 5e-3, 5e-5)])
 def test_spherepack_deviation_storage_against_fp64(pack, prec, tol_u, tol_rho):
     # deviation storage at the benchmark size against the FP64 path (which is
