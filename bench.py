@@ -177,7 +177,16 @@ def traffic_from(fetch_csv, write_csv, workload_name, command):
     return doc
 
 
-def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_remap=True):
+def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_remap=True, sample_every=16):
+    """Time `steps` cycles of two time steps each, queued back to back.
+
+    Returns (wall seconds, even-step durations, odd-step durations, index).
+    Kernel durations come from HIP events on the solver's stream around
+    single launches inside the timed run: the first step of every
+    `sample_every`-th cycle and the second step of the cycle half-way
+    between. Events around every launch would slow the run itself (4 % in
+    FP64 and 7 % in FP32 on the sphere pack); sampled, they cost about
+    0.2 %."""
     from paper_1410_0412_amd import Solver
 
     s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=precision, xcd_remap=xcd_remap)
@@ -185,22 +194,33 @@ def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_rema
     s.init()
     s.step(2 * warmup)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+    every = max(1, int(sample_every))
+    half = every // 2
+    pairs = ([], [])  # (start, end) events around first / second steps
     t0 = time.perf_counter()
-    ev[0].record()
     for i in range(steps):
-        s.step(1)
-        ev[2 * i + 1].record()
-        s.step(1)
-        ev[2 * i + 2].record()
+        k = i % every
+        sample = (k == 0, k == half if every > 1 else True)
+        if not any(sample):
+            s.step(2)
+            continue
+        for j in (0, 1):
+            if not sample[j]:
+                s.step(1)
+                continue
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            s.step(1)
+            b.record()
+            pairs[j].append((a, b))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    d = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(2 * steps)]) * 1e-3
+    d = [np.array([a.elapsed_time(b) for a, b in pr]) * 1e-3 for pr in pairs]
     _, _, tot = s.moments()
     if not np.isfinite(tot.cpu().numpy()).all():
         raise RuntimeError("non-finite totals after the timed run")
     del s
-    return wall, d[0::2], d[1::2], index
+    return wall, d[0], d[1], index
 
 
 def microbench(torch, n_nodes):
@@ -315,6 +335,40 @@ def order_sweep(torch, args):
         log(spec, row)
         out["orders"][spec] = row
         del lat
+    print(json.dumps(out), flush=True)
+
+
+def size_sweep(torch, args):
+    """AA-RIA throughput against lattice size: steps queued back to back, as a
+    caller runs them, timed with events around the whole run."""
+    from lbm_inputs import workload
+    from paper_1410_0412_amd import Lattice, Solver
+
+    out = {"metric": "MFLUP/s against lattice size (AA-RIA, automatic index choice)", "unit": "MFLUP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "workloads": {}}
+    for name in args.size_sweep.split(","):
+        log("generating", name)
+        mask, p = workload(name, seed=args.seed)
+        lat = Lattice(mask, p["periodic"], p["order"], p["block"])
+        N = lat.n_fluid
+        row = {"fluid_nodes": N}
+        for prec in ("f64", "f32"):
+            s = Solver(lat, p["tau"], p["force"], pattern="aa", ria="auto", precision=prec)
+            s.init()
+            s.step(2 * args.warmup)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.step(2 * args.steps)
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+            row[prec] = {"index": s.index, "mflups": round(2 * args.steps * N / sec / 1e6, 1),
+                         "us_per_time_step": round(sec / (2 * args.steps) * 1e6, 2)}
+            del s
+        log(name, row)
+        out["workloads"][name] = row
+        del lat, mask
     print(json.dumps(out), flush=True)
 
 
@@ -501,6 +555,8 @@ def main():
                     help="micro-benchmarks only, at these node counts (comma separated), one JSON line")
     ap.add_argument("--stride-sweep", action="store_true",
                     help="U-19A bandwidth against the padding of the stream stride")
+    ap.add_argument("--size-sweep", default=None,
+                    help="AA-RIA FP64/FP32 MFLUP/s on these workloads (comma separated), one JSON line")
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32/FP16 deviation storage vs FP64 after --steps time steps on --workload")
     args = ap.parse_args()
@@ -525,6 +581,8 @@ def main():
         return order_sweep(torch, args)
     if args.precision_study:
         return precision_study(torch, args)
+    if args.size_sweep:
+        return size_sweep(torch, args)
     if args.stride_sweep:
         return stride_sweep(torch, args)
     if args.adjoint:
