@@ -22,6 +22,11 @@ LIB = os.path.join(HERE, "liblbm_sparse.so")
 SOURCES = ["lattice.cpp", "solver.hip"]
 HEADERS = ["common.hpp", "d3q19.hpp", "kernels.hpp", "adjoint.hpp"]
 
+# the C ABI driven from C++ without Python (host code only)
+DRIVER_SOURCE = "lbm_run.cpp"
+DRIVER = os.path.join(HERE, "lbm_run")
+DRIVER_FLAGS = ["-O2", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE]
+
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-pthread",
     "-ffp-contract=off",
@@ -37,17 +42,26 @@ def hipcc():
     return exe
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every source into ``liblbm_sparse.so``; returns its path."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + FLAGS + list(extra) + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def _run(cmd, verbose, what):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building liblbm_sparse.so")
+        raise RuntimeError("hipcc failed building " + what)
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile every source into ``liblbm_sparse.so``, then the command-line
+    driver ``lbm_run`` against it; returns the library's path."""
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run([hipcc()] + FLAGS + list(extra) + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp],
+         verbose, "liblbm_sparse.so")
     os.replace(tmp, LIB)
+    tmp = DRIVER + ".tmp%d" % os.getpid()
+    _run([hipcc()] + DRIVER_FLAGS + [os.path.join(CSRC, DRIVER_SOURCE), "-L", HERE, "-llbm_sparse",
+                                     "-Wl,-rpath,$ORIGIN", "-o", tmp], verbose, "lbm_run")
+    os.replace(tmp, DRIVER)
     return LIB
 
 

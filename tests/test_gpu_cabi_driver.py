@@ -1,0 +1,90 @@
+"""The C ABI driven without Python: ``lbm_run`` (C++ over include/lbm_sparse.h
+and the HIP runtime, with device buffers it allocates itself) builds the
+lattice, runs a solver from the rest state and writes f(t). Its output must
+equal the oracle's dense solver bitwise in FP64, and stay within the
+deviation-storage bound in FP32."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from lbm_inputs import rsa_spheres
+from oracle import dense
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DRIVER = os.path.join(ROOT, "paper_1410_0412_amd", "lbm_run")
+PER = (True, False, False)
+TAU, FORCE = 0.8, (1e-5, 2e-6, 0.0)
+
+
+def run_driver(tmp_path, mask, order, block, pattern, index, prec, steps, mask_bytes=None):
+    if not os.path.exists(DRIVER):
+        pytest.fail("lbm_run is not built (run the package's build.py)")
+    mpath = tmp_path / "mask.u8"
+    mpath.write_bytes(mask_bytes if mask_bytes is not None else mask.astype(np.uint8).tobytes())
+    out = tmp_path / "f.bin"
+    bits = sum(1 << a for a in range(3) if PER[a])
+    cmd = [DRIVER, str(mpath)] + [str(n) for n in mask.shape] + [str(bits), order, str(block), pattern, index, prec,
+                                                                  repr(TAU)] + [repr(v) for v in FORCE] + [
+        str(steps), str(out)]
+    print("case lbm_run", order, block, pattern, index, prec, steps, flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
+    return r, out
+
+
+def read_output(out):
+    raw = out.read_bytes()
+    N = int(np.frombuffer(raw[:8], np.int64)[0])
+    nv = np.frombuffer(raw[8:8 + 4 * N], np.int32).astype(np.int64)
+    f = np.frombuffer(raw[8 + 4 * N:], np.float64).reshape(19, N)
+    return nv, f
+
+
+@pytest.fixture(scope="module")
+def case():
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.2, PER, seed=5)
+    steps = 7
+    ref = dense.run(mask.astype(bool), PER, TAU, FORCE, steps)
+    return mask, steps, ref.reshape(19, -1)
+
+
+@pytest.mark.parametrize("pattern", ["aa", "osnt"])
+@pytest.mark.parametrize("index", ["adjacency", "runs", "direction"])
+def test_driver_fp64_bitwise(tmp_path, case, pattern, index):
+    mask, steps, ref = case
+    r, out = run_driver(tmp_path, mask, "lex", 0, pattern, index, "f64", steps)
+    assert r.returncode == 0, r.stderr
+    nv, f = read_output(out)
+    assert len(nv) == int((mask == 0).sum())
+    assert np.array_equal(f, ref[:, nv])
+    # the totals line: mass of f(t), FP64, deterministic reduction
+    mass = float(r.stdout.split("mass=")[1].split()[0])
+    want = f.sum()
+    assert abs(mass - want) <= 1e-13 * want
+
+
+def test_driver_morton_and_fp32(tmp_path, case):
+    mask, steps, ref = case
+    r, out = run_driver(tmp_path, mask, "morton", 0, "aa", "runs", "f64", steps)
+    assert r.returncode == 0, r.stderr
+    nv, f = read_output(out)
+    assert np.array_equal(f, ref[:, nv])
+    r, out = run_driver(tmp_path, mask, "lex", 4, "aa", "direction", "f32", steps)
+    assert r.returncode == 0, r.stderr
+    nv, f = read_output(out)
+    # deviation storage: deviations here are O(steps * w * |F|) ~ 1e-5, each
+    # rounded to FP32 (2^-24 relative) once per step and collided in FP32
+    err = np.max(np.abs(f - ref[:, nv]))
+    print("lbm_run FP32 max |f - f_oracle| = %.3e" % err, flush=True)
+    assert err <= 1e-9
+
+
+def test_driver_rejects_bad_input(tmp_path, case):
+    mask, steps, _ = case
+    r, _ = run_driver(tmp_path, mask, "lex", 0, "aa", "runs", "f64", steps, mask_bytes=b"\0" * 10)
+    assert r.returncode == 1 and "mask size" in r.stderr
+    r, _ = run_driver(tmp_path, mask, "zigzag", 0, "aa", "runs", "f64", steps)
+    assert r.returncode == 1 and "unknown order" in r.stderr
