@@ -2,6 +2,7 @@
 checks its parameters before it touches the device, so invalid calls can be
 exercised with placeholder pointers that are never dereferenced."""
 import ctypes
+import os
 
 import pytest
 
@@ -115,3 +116,31 @@ def test_null_handles():
     assert L.lbm_solver_time(None, ctypes.byref(t)) == capi.LBM_EINVAL
     assert L.lbm_solver_moments(None, None, None, None) == capi.LBM_EINVAL
     assert L.lbm_lattice_sizes(None, None, None, None) == capi.LBM_EINVAL
+
+
+def test_driver_rejects_bad_arguments(tmp_path):
+    # lbm_run checks its arguments and the mask file before any HIP call
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    driver = os.path.join(root, "paper_1410_0412_amd", "lbm_run")
+    assert os.path.exists(driver), "lbm_run is not built (run the package's build.py)"
+    mask = tmp_path / "mask.u8"
+    mask.write_bytes(b"\0" * 10)
+    out = str(tmp_path / "f.bin")
+
+    def run(*args):
+        return subprocess.run([driver] + [str(a) for a in args], capture_output=True, text=True, timeout=60)
+
+    r = run()
+    assert r.returncode == 1 and "usage" in r.stderr
+    good = [mask, 2, 2, 2, 1, "lex", 0, "aa", "runs", "f64", 0.8, 0, 0, 0, 1, out]
+    r = run(*good)  # 10 bytes for a 2x2x2 box
+    assert r.returncode == 1 and "mask size" in r.stderr
+    for pos, bad, msg in ((5, "zigzag", "unknown order"), (7, "push", "unknown pattern"),
+                          (8, "list", "unknown index source"), (9, "f8", "unknown precision"),
+                          (1, 0, "bad extents")):
+        args = list(good)
+        args[pos] = bad
+        r = run(*args)
+        assert r.returncode == 1 and msg in r.stderr, (bad, r.stderr)

@@ -80,11 +80,3 @@ def test_driver_morton_and_fp32(tmp_path, case):
     err = np.max(np.abs(f - ref[:, nv]))
     print("lbm_run FP32 max |f - f_oracle| = %.3e" % err, flush=True)
     assert err <= 1e-9
-
-
-def test_driver_rejects_bad_input(tmp_path, case):
-    mask, steps, _ = case
-    r, _ = run_driver(tmp_path, mask, "lex", 0, "aa", "runs", "f64", steps, mask_bytes=b"\0" * 10)
-    assert r.returncode == 1 and "mask size" in r.stderr
-    r, _ = run_driver(tmp_path, mask, "zigzag", 0, "aa", "runs", "f64", steps)
-    assert r.returncode == 1 and "unknown order" in r.stderr
