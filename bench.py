@@ -81,11 +81,11 @@ def _strip_comments(text):
 def source_digest(read=None):
     """Digest of the kernel sources (comments and layout ignored), so that
     counter results are only reused for the code they were taken on."""
-    from paper_1410_0412_amd.build import HEADERS, SOURCES
+    from paper_1410_0412_amd.build import DEVICE_SOURCES
 
     csrc = os.path.join(ROOT, "paper_1410_0412_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(set(SOURCES) | set(HEADERS)):
+    for name in sorted(DEVICE_SOURCES):
         if read is None:
             with open(os.path.join(csrc, name), encoding="utf-8") as fh:
                 text = fh.read()

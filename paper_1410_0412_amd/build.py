@@ -21,6 +21,8 @@ LIB = os.path.join(HERE, "liblbm_sparse.so")
 
 SOURCES = ["lattice.cpp", "solver.hip"]
 HEADERS = ["common.hpp", "d3q19.hpp", "kernels.hpp", "adjoint.hpp"]
+# the files the GPU kernels are compiled from (lattice.cpp is host code)
+DEVICE_SOURCES = ["solver.hip"] + HEADERS
 
 # the C ABI driven from C++ without Python (host code only)
 DRIVER_SOURCE = "lbm_run.cpp"

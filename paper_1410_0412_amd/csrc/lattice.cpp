@@ -16,7 +16,9 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <exception>
 #include <new>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -46,6 +48,10 @@ constexpr int kC[19][3] = {
     {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
     {-1, 0, 1}, {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
 
+// Run body(lo, hi) over [0, n) in up to 32 contiguous ranges on threads.
+// Ranges that get no thread (thread creation failed) run on the calling
+// thread. Every thread is joined before the first exception of any range is
+// rethrown.
 template <class F>
 void parallel_for(int64_t n, F&& body) {
   unsigned hw = std::thread::hardware_concurrency();
@@ -55,14 +61,30 @@ void parallel_for(int64_t n, F&& body) {
     body(int64_t(0), n);
     return;
   }
+  const int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::exception_ptr> err((size_t)nt);
   std::vector<std::thread> th;
-  int64_t chunk = (n + nt - 1) / nt;
-  for (int64_t t = 0; t < nt; ++t) {
-    int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
-    if (lo >= hi) break;
-    th.emplace_back([&body, lo, hi] { body(lo, hi); });
+  th.reserve((size_t)nt);
+  auto range = [&](int64_t t) {
+    const int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+    try {
+      if (lo < hi) body(lo, hi);
+    } catch (...) {
+      err[(size_t)t] = std::current_exception();
+    }
+  };
+  int64_t t = 0;
+  for (; t < nt; ++t) {
+    try {
+      th.emplace_back(range, t);
+    } catch (const std::system_error&) {
+      break;
+    }
   }
+  for (; t < nt; ++t) range(t);
   for (auto& x : th) x.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
 }
 
 inline uint64_t spread3(uint64_t v) {
@@ -355,6 +377,9 @@ int lbm_lattice_build(const uint8_t* solid, int32_t nx, int32_t ny, int32_t nz,
   } catch (const std::bad_alloc&) {
     delete L;
     return fail(LBM_ENOMEM, "out of host memory building the lattice");
+  } catch (const std::exception& e) {
+    delete L;
+    return fail(LBM_ENOMEM, "host resources exhausted building the lattice: %s", e.what());
   }
   *out = L;
   return LBM_OK;
