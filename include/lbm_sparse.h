@@ -294,6 +294,19 @@ int lbm_adjoint_seed_momentum(lbm_solver* s, const double* weight, int32_t axis,
                               double* lam);
 
 /*
+ * One AA step t -> t+1 that also writes the PDFs f(t) it reads into save
+ * (device double[19*ldf], not the solver's grid): afterwards save holds, at
+ * every slot of a fluid node, what the AA grid held before the step, which is
+ * the forward state lbm_adjoint_step needs for step t. Slots of the padding
+ * nodes N..ldf-1 are not written. The step itself is that of
+ * lbm_solver_step(s, 1): with partial bounce-back if the solver has a
+ * solid-fraction buffer, else the plain step (bitwise). It costs 8 B per PDF
+ * written, against a read and a write per PDF for a copy of the grid.
+ * Asynchronous. LBM_ESTATE unless AA, FP64 and BGK.
+ */
+int lbm_solver_step_save(lbm_solver* s, double* save);
+
+/*
  * Backward through the step t -> t+1. fwd: device double[19*ldf], the AA grid
  * holding f(t) (as the solver held it before stepping from t). lam: on entry
  * dJ/df(t+1) in the layout of time t+1, on exit dJ/df(t) in the layout of

@@ -104,6 +104,7 @@ def lib():
         "lbm_solver_weighted_momentum": (ctypes.c_int, [vp, vp, ctypes.c_int32, vp]),
         "lbm_adjoint_seed_momentum": (ctypes.c_int, [vp, vp, ctypes.c_int32, ctypes.c_int64, vp]),
         "lbm_adjoint_step": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
+        "lbm_solver_step_save": (ctypes.c_int, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -121,6 +122,7 @@ EXPORTED = [
     "lbm_solver_init_equilibrium", "lbm_solver_step", "lbm_solver_time", "lbm_solver_moments",
     "lbm_solver_export_pdfs", "lbm_solver_import_pdfs", "lbm_solver_free", "lbm_bench_stream",
     "lbm_solver_set_time", "lbm_solver_weighted_momentum", "lbm_adjoint_seed_momentum", "lbm_adjoint_step",
+    "lbm_solver_step_save",
 ]
 
 

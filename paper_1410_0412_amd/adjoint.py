@@ -5,8 +5,9 @@ kernels (``lbm_adjoint_*``) with checkpointed recomputation.
 J(ns) = sum_n weight[n] * j_axis(n, T) after T AA steps from the rest state.
 The forward pass stores the AA grid every ``every`` steps. The backward pass
 walks the segments from last to first: it restores a checkpoint, recomputes
-the segment storing each grid, and runs the adjoint step over those grids in
-reverse. Device memory: ceil(T / every) + every grids.
+the segment with steps that also store the state each of them reads, and runs
+the adjoint step over those states in reverse. Device memory:
+ceil(T / every) + every grids.
 """
 
 from __future__ import annotations
@@ -47,14 +48,14 @@ class OutletFlux(torch.autograd.Function):
         lam = torch.empty_like(s.pdf[0])
         grad = torch.zeros(s.n_fluid, dtype=torch.float64, device=s.device)
         s.adjoint_seed(weight, ctx.axis, T, lam)
+        # the recomputed states of one segment; each step writes its f(t)
+        states = [torch.empty_like(s.pdf[0]) for _ in range(min(every, T))]
         for t0, ck in reversed(ctx.ckpts):
             t1 = min(t0 + every, T)
             s.pdf[0].copy_(ck)
             s.set_time(t0)
-            states = []
-            for _ in range(t0, t1):
-                states.append(s.pdf[0].clone())
-                s.step(1)
+            for t in range(t0, t1):
+                s.step_save(states[t - t0])
             for t in range(t1 - 1, t0 - 1, -1):
                 s.adjoint_step(states[t - t0], t, lam, grad)
         ctx.ckpts = None

@@ -36,10 +36,13 @@ __device__ __forceinline__ void step_slots(int32_t n, const Idx& idx, int32_t (&
   }
 }
 
-template <class Idx, bool ODD>
+// One AA step with partial bounce-back (ns = NULL: every ns is 0). SAVE
+// also writes the PDFs f(t) it reads into `save`, in the grid's slots of
+// time t: the forward state the adjoint of this step reads.
+template <class Idx, bool ODD, bool SAVE>
 __global__ void __launch_bounds__(kBlock)
 aa_step_pbb(double* __restrict__ F, int32_t N, Idx idx, Collision c,
-            const double* __restrict__ ns, int chunk) {
+            const double* __restrict__ ns, double* __restrict__ save, int chunk) {
   const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
@@ -48,8 +51,12 @@ aa_step_pbb(double* __restrict__ F, int32_t N, Idx idx, Collision c,
   double f[Q], fs[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = fs[q] = F[g[q]];
+  if constexpr (SAVE) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) save[g[q]] = f[q];
+  }
   collide_f64(fs, c);
-  const double s = ns[n];
+  const double s = ns ? ns[n] : 0.0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) F[g[kOpp[q]]] = ((1.0 - s) * fs[q]) + (s * f[kOpp[q]]);
 }

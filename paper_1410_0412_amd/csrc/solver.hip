@@ -406,19 +406,24 @@ void launch_step_op(lbm_solver* s, int32_t N) {
   }
 }
 
-void launch_step_pbb(lbm_solver* s, int32_t N) {
+// The partial-bounce-back step (AA, FP64, BGK); save != NULL also writes
+// f(t) into save.
+void launch_step_pbb(lbm_solver* s, int32_t N, double* save) {
   double* F = (double*)s->b.pdf[0];
   // the odd step's tile order (the even step of the PBB path shares it)
   const int chunk = s->remap ? kOddChunk : 0;
   const dim3 grid(chunked_grid(grid_for(N), chunk));
   auto go = [&](auto idx) {
     using I = decltype(idx);
-    if (s->t % 2 == 0)
-      hipLaunchKernelGGL((aa_step_pbb<I, false>), grid, dim3(kBlock), 0, s->stream, F, N, idx, s->c,
-                         s->b.solid_frac, chunk);
+    auto launch = [&](auto odd, auto keep) {
+      hipLaunchKernelGGL((aa_step_pbb<I, decltype(odd)::value, decltype(keep)::value>), grid, dim3(kBlock), 0,
+                         s->stream, F, N, idx, s->c, s->b.solid_frac, save, chunk);
+    };
+    const bool odd = s->t % 2 != 0;
+    if (save)
+      odd ? launch(std::true_type{}, std::true_type{}) : launch(std::false_type{}, std::true_type{});
     else
-      hipLaunchKernelGGL((aa_step_pbb<I, true>), grid, dim3(kBlock), 0, s->stream, F, N, idx, s->c,
-                         s->b.solid_frac, chunk);
+      odd ? launch(std::true_type{}, std::false_type{}) : launch(std::false_type{}, std::false_type{});
   };
   with_index(s, go);
 }
@@ -426,7 +431,7 @@ void launch_step_pbb(lbm_solver* s, int32_t N) {
 int launch_step(lbm_solver* s) {
   const int32_t N = (int32_t)s->p.n_fluid;
   if (N > 0 && s->b.solid_frac) {
-    launch_step_pbb(s, N);
+    launch_step_pbb(s, N, nullptr);
   } else if (N > 0) {
     if (s->trt)
       launch_step_op<true>(s, N);
@@ -691,6 +696,17 @@ int lbm_adjoint_seed_momentum(lbm_solver* s, const double* weight, int32_t axis,
   };
   with_index(s, go);
   return device_status("adjoint_seed_momentum");
+}
+
+int lbm_solver_step_save(lbm_solver* s, double* save) {
+  clear_error();
+  if (!s || !save) return fail(LBM_EINVAL, "null pointer");
+  int rc = adjoint_ready(s);
+  if (rc) return rc;
+  const int32_t N = (int32_t)s->p.n_fluid;
+  if (N > 0) launch_step_pbb(s, N, save);
+  s->t += 1;
+  return device_status("step_save");
 }
 
 int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, double* grad) {

@@ -246,6 +246,17 @@ class Solver:
         self._call(_capi.lib().lbm_adjoint_seed_momentum, _vp(w), int(axis), int(t), _vp(lam))
         self._keep = (w,)
 
+    def step_save(self, save):
+        """One AA step that also writes the PDFs f(t) it reads into ``save``
+        (a float64 grid like ``pdf[0]``): the forward state
+        :meth:`adjoint_step` needs for step t. AA, FP64 and BGK only."""
+        torch = self.torch
+        if save.dtype != torch.float64 or save.device != self.device or save.numel() < 19 * self.ldf \
+                or not save.is_contiguous():
+            raise ValueError("save must be a contiguous float64 tensor of %d elements on %s" % (19 * self.ldf,
+                                                                                               self.device))
+        self._call(_capi.lib().lbm_solver_step_save, _vp(save))
+
     def adjoint_step(self, fwd, t, lam, grad):
         self._call(_capi.lib().lbm_adjoint_step, _vp(fwd), int(t), _vp(lam), _vp(grad))
 

@@ -56,6 +56,48 @@ def test_pbb_zero_fraction_is_plain_step(small):
     assert np.array_equal(a.export_pdfs().cpu().numpy(), b.export_pdfs().cpu().numpy())
 
 
+def fluid_slots(n_fluid):
+    """Element offsets of every (q, n) slot of the fluid nodes in the
+    tile-major grid: direction q of node n = 64t + l at (19t + q)*64 + l."""
+    n = np.arange(n_fluid)
+    return (((19 * (n // 64))[None, :] + np.arange(19)[:, None]) * 64 + (n % 64)[None, :]).reshape(-1)
+
+
+@pytest.mark.parametrize("ria", [False, True, "direction"])
+@pytest.mark.parametrize("pbb", [True, False])
+def test_step_save(small, ria, pbb):
+    # step_save keeps the state each step reads and steps exactly like step
+    mask, ns, _ = small
+    lat, a = solver_for(mask, PER, 0.8, (1e-5, 0, 0), "aa", ria, pbb=pbb)
+    _, b = solver_for(mask, PER, 0.8, (1e-5, 0, 0), "aa", ria, pbb=pbb)
+    if pbb:
+        x = torch.from_numpy(nodes_of(lat, ns)).cuda()
+        a.set_solid_fraction(x)
+        b.set_solid_fraction(x)
+    a.init()
+    b.init()
+    idx = torch.from_numpy(fluid_slots(lat.n_fluid)).cuda()
+    save = torch.full_like(a.pdf[0], float("nan"))
+    for t in range(5):  # both parities
+        before = a.pdf[0].clone()
+        a.step_save(save)
+        b.step(1)
+        assert torch.equal(save[idx], before[idx]), t
+        assert torch.equal(a.pdf[0][idx], b.pdf[0][idx]), t
+    assert a.t == b.t == 5
+
+
+def test_step_save_needs_aa_fp64_bgk(small):
+    from paper_1410_0412_amd import LbmError
+    mask, _, _ = small
+    for kw in (dict(pattern="osnt"), dict(pattern="aa", precision="f32"), dict(pattern="aa", trt_magic=0.25)):
+        pattern = kw.pop("pattern")
+        _, s = solver_for(mask, PER, 0.8, (1e-5, 0, 0), pattern, True, **kw)
+        s.init()
+        with pytest.raises(LbmError):
+            s.step_save(torch.empty(19 * s.ldf, dtype=torch.float64, device="cuda"))
+
+
 @pytest.mark.parametrize("ria", [False, True, "direction"])
 @pytest.mark.parametrize("every", [1, 5, 12])
 def test_gradient_matches_autograd(small, ria, every):
