@@ -31,10 +31,9 @@ class OutletFlux(torch.autograd.Function):
         solver.set_solid_fraction(ns.detach())
         solver.init()
         ckpts = []
-        for t in range(steps):
-            if t % every == 0:
-                ckpts.append((t, solver.pdf[0].clone()))
-            solver.step(1)
+        for t0 in range(0, steps, every):
+            ckpts.append((t0, solver.pdf[0].clone()))
+            solver.step(min(every, steps - t0))
         J = solver.weighted_momentum(weight, axis)
         ctx.solver, ctx.steps, ctx.every, ctx.axis = solver, steps, every, axis
         ctx.ckpts = ckpts
