@@ -374,6 +374,32 @@ def size_sweep(torch, args):
     print(json.dumps(out), flush=True)
 
 
+def pattern_study(torch, args):
+    """AA against OS-NT (RIA, automatic index choice) per storage precision
+    on each workload of --pattern-study."""
+    from lbm_inputs import workload
+    from paper_1410_0412_amd import Lattice
+
+    out = {"metric": "MFLUP/s of AA-RIA and OS-NT-RIA per storage precision", "unit": "MFLUP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "workloads": {}}
+    for name in args.pattern_study.split(","):
+        log("generating", name)
+        mask, p = workload(name, seed=args.seed)
+        lat = Lattice(mask, p["periodic"], p["order"], p["block"])
+        N = lat.n_fluid
+        row = {"fluid_nodes": N}
+        for prec in ("f64", "f32", "f16"):
+            for pattern in ("aa", "osnt"):
+                wall, d_a, d_b, index = time_variant(torch, lat, p, pattern, "auto", prec, args.steps, args.warmup)
+                row["%s_%s" % (pattern, prec)] = {
+                    "index": index, "mflups": round(2 * N * args.steps / wall / 1e6, 1),
+                    "kernel_us": [round(float(np.mean(d_a)) * 1e6, 2), round(float(np.mean(d_b)) * 1e6, 2)]}
+        log(name, row)
+        out["workloads"][name] = row
+        del lat, mask
+    print(json.dumps(out), flush=True)
+
+
 def precision_study(torch, args):
     """FP32 / FP16 deviation storage against the FP64 path on one workload."""
     from lbm_inputs import workload
@@ -557,6 +583,8 @@ def main():
                     help="micro-benchmarks only, at these node counts (comma separated), one JSON line")
     ap.add_argument("--stride-sweep", action="store_true",
                     help="U-19A bandwidth against the padding of the stream stride")
+    ap.add_argument("--pattern-study", default=None,
+                    help="AA and OS-NT (RIA) in FP64/FP32/FP16 on these workloads (comma separated), one JSON line")
     ap.add_argument("--size-sweep", default=None,
                     help="AA-RIA FP64/FP32 MFLUP/s on these workloads (comma separated), one JSON line")
     ap.add_argument("--precision-study", action="store_true",
@@ -585,6 +613,8 @@ def main():
         return precision_study(torch, args)
     if args.size_sweep:
         return size_sweep(torch, args)
+    if args.pattern_study:
+        return pattern_study(torch, args)
     if args.stride_sweep:
         return stride_sweep(torch, args)
     if args.adjoint:
