@@ -155,35 +155,45 @@ def test_spherepack_deviation_storage_against_fp64(pack, prec, tol_u, tol_rho):
     assert du <= tol_u and drho <= tol_rho and abs(ml - m64) / m64 <= 1e-6
 
 
-def test_maximum_size_lattice():
+@pytest.fixture(scope="module")
+def maxcase():
     # the largest lattice the 32-bit slot offsets allow: a fully fluid
     # periodic 480 x 480 x 490 box, N = 112,896,000 nodes, 19 * ldf just
-    # below 2^31 - 1; sampled sites (including the last node) after 3 steps
-    # against the oracle's dependency cone, bitwise
+    # below 2^31 - 1
     shape = (480, 480, 490)
     per = (True, True, True)
     tau, force, steps = 0.7, (1e-6, 0.0, 0.0), 3
     mask = np.zeros(shape, np.uint8)
     print("case maximum size: building the lattice", flush=True)
-    from paper_1410_0412_amd import Lattice, Solver
+    from paper_1410_0412_amd import Lattice
     lat = Lattice(mask, per, "lex", 0)
     N = lat.n_fluid
     assert N == 480 * 480 * 490 and 19 * ((N + 63) // 64 * 64) <= 2 ** 31 - 1
-    s = Solver(lat, tau, force, pattern="aa", ria="auto")
     rho0, u0 = init_fields(shape, seed=41)
     r, v = node_fields(lat, rho0, u0)
-    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
-    del r, v
-    print("case maximum size: stepping, index", s.index, flush=True)
-    s.step(steps)
     rng = np.random.default_rng(42)
     sites = np.stack([rng.integers(0, n, 30) for n in shape], 1)
     sites = np.concatenate([sites, [[479, 479, 489], [0, 0, 0]]])
     want = dense.cone_sites(mask.astype(bool), per, tau, force, steps, rho0, u0, sites)
     del rho0, u0
-    node = torch.from_numpy((sites[:, 0] * shape[1] + sites[:, 1]) * shape[2] + sites[:, 2]).cuda()
+    node = (sites[:, 0] * shape[1] + sites[:, 1]) * shape[2] + sites[:, 2]
+    return lat, per, tau, force, steps, r, v, node, want
+
+
+@pytest.mark.parametrize("pattern,ria", [("aa", "auto"), ("osnt", "auto"), ("aa", False), ("osnt", "direction")])
+def test_maximum_size_lattice(maxcase, pattern, ria):
+    # sampled sites (including the last node) after 3 steps against the
+    # oracle's dependency cone, bitwise
+    from paper_1410_0412_amd import Solver
+    lat, per, tau, force, steps, r, v, node, want = maxcase
+    s = Solver(lat, tau, force, pattern=pattern, ria=ria)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    print("case maximum size:", pattern, "index", s.index, flush=True)
+    s.step(steps)
     f = s.export_pdfs()
-    got = f[:, node].T.cpu().numpy()
+    got = f[:, torch.from_numpy(node).cuda()].T.cpu().numpy()
+    del s, f
+    torch.cuda.empty_cache()
     assert np.array_equal(got, want)
 
 
