@@ -302,7 +302,8 @@ int lbm_adjoint_seed_momentum(lbm_solver* s, const double* weight, int32_t axis,
  * lbm_solver_step(s, 1): with partial bounce-back if the solver has a
  * solid-fraction buffer, else the plain step (bitwise). It costs 8 B per PDF
  * written, against a read and a write per PDF for a copy of the grid.
- * Asynchronous. LBM_ESTATE unless AA, FP64 and BGK.
+ * Asynchronous. LBM_EINVAL for a null pointer or save equal to the grid;
+ * LBM_ESTATE unless AA, FP64 and BGK.
  */
 int lbm_solver_step_save(lbm_solver* s, double* save);
 

@@ -703,6 +703,7 @@ int lbm_solver_step_save(lbm_solver* s, double* save) {
   if (!s || !save) return fail(LBM_EINVAL, "null pointer");
   int rc = adjoint_ready(s);
   if (rc) return rc;
+  if (save == s->b.pdf[0]) return fail(LBM_EINVAL, "save must not be the solver's grid");
   const int32_t N = (int32_t)s->p.n_fluid;
   if (N > 0) launch_step_pbb(s, N, save);
   s->t += 1;

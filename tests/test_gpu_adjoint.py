@@ -90,6 +90,10 @@ def test_step_save(small, ria, pbb):
 def test_step_save_needs_aa_fp64_bgk(small):
     from paper_1410_0412_amd import LbmError
     mask, _, _ = small
+    _, s = solver_for(mask, PER, 0.8, (1e-5, 0, 0), "aa", True, pbb=True)
+    s.init()
+    with pytest.raises(LbmError):
+        s.step_save(s.pdf[0])  # the solver's own grid
     for kw in (dict(pattern="osnt"), dict(pattern="aa", precision="f32"), dict(pattern="aa", trt_magic=0.25)):
         pattern = kw.pop("pattern")
         _, s = solver_for(mask, PER, 0.8, (1e-5, 0, 0), pattern, True, **kw)
