@@ -186,3 +186,24 @@ def test_totals_are_reproducible():
     for a in range(3):
         j = math.fsum((C[:, a][:, None] * f).reshape(-1))
         assert abs(seen[1 + a] - j) <= 1e-14 * mass, a
+
+
+def test_work_runs_on_the_current_stream():
+    # the binding queues every call on torch's current stream; a solver
+    # driven on a side stream gives the default-stream result bitwise
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.2, PER, seed=3)
+    lat, a = solver_for(mask, PER, 0.8, (1e-5, 0.0, 0.0), "aa", "direction")
+    _, b = solver_for(mask, PER, 0.8, (1e-5, 0.0, 0.0), "aa", "direction")
+    a.init()
+    a.step(9)
+    fa = a.export_pdfs()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.init()
+        b.step(9)
+        fb = b.export_pdfs()
+        _, _, tb = b.moments()
+    torch.cuda.current_stream().wait_stream(side)
+    assert torch.equal(fa, fb)
+    assert torch.equal(a.moments()[2], tb)
