@@ -123,10 +123,10 @@ def kernel_key(name):
     return "".join(out).strip()
 
 
-def traffic_from(fetch_csv, write_csv, workload_name, command):
-    """Write profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE,
-    WRITE_SIZE; KiB per dispatch). Both counters are scaled by what they read
-    for the copy micro-benchmark, whose bytes are known."""
+def traffic_from(fetch_csv, write_csv, workload_name, command, out_path=None):
+    """Write profiles/traffic.json (or out_path) from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch). Both counters are scaled by
+    what they read for the copy micro-benchmark, whose bytes are known."""
     import csv
 
     def load(path, counter):
@@ -174,7 +174,7 @@ def traffic_from(fetch_csv, write_csv, workload_name, command):
            "scale": {"fetch": round(sf, 4), "write": round(sw, 4),
                      "reference": "copy micro-benchmark of %d bytes" % copy_bytes},
            "command": command, "kernels": kernels}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(doc, fh, indent=1)
     return doc
 

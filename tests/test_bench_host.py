@@ -1,0 +1,90 @@
+"""Host logic of the benchmark: the algorithmic bytes the roofline divides by,
+the digest that ties counter results to the kernel sources, and the scaling
+and grouping of rocprofv3 counter rows."""
+import csv
+import json
+
+import pytest
+
+import bench
+from lbm_inputs import rsa_spheres
+
+
+def test_kernel_bytes_match_the_table_sizes():
+    # one launch moves the 19 PDFs in and out (38 s B per node) plus the index
+    # tables: 72 B per node (adjacency), 72 B per run + 12 B per tile (the
+    # paper's runs), 4 B per direction run + 216 B per tile (per-direction)
+    from paper_1410_0412_amd import Lattice
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.2, (True, False, False), seed=5)
+    lat = Lattice(mask, (True, False, False), "lex", 0)
+    N, R, W, RD = lat.n_fluid, lat.n_runs, lat.n_waves, lat.n_direction_runs
+    ib = lat.index_bytes()
+    assert W == (N + 63) // 64
+    want = {"adjacency": 72 * N, "runs": 72 * R + 12 * W, "direction": 4 * RD + 216 * W}
+    for index, extra in want.items():
+        for s in (8, 4, 2):
+            assert bench.kernel_bytes("even", N, ib[index], s) == 38 * s * N
+            for kind in ("odd", "osnt"):
+                assert bench.kernel_bytes(kind, N, ib[index], s) == pytest.approx(38 * s * N + extra, rel=1e-12)
+    with pytest.raises(KeyError):
+        bench.kernel_bytes("copy", N, 0.0)
+
+
+def test_source_digest_ignores_comments_and_layout():
+    base = {"solver.hip": 'int f(int x) {\n  return x + 1;  // one\n}\nconst char* s = "// not a comment";\n'}
+    digest = lambda files: bench.source_digest(read=lambda name: files.get(name, ""))
+    d0 = digest(base)
+    same = {"solver.hip": '/* header */\nint  f(int x)   {\n\n    return x + 1;\n}\nconst char* s = "// not a comment";'}
+    assert digest(same) == d0
+    assert digest({"solver.hip": base["solver.hip"].replace("x + 1", "x + 2")}) != d0
+    assert digest({"solver.hip": base["solver.hip"].replace('"// not a comment"', '"//"')}) != d0
+
+
+def test_source_digest_covers_the_device_sources():
+    from paper_1410_0412_amd.build import DEVICE_SOURCES, HEADERS
+    seen = []
+    bench.source_digest(read=lambda name: seen.append(name) or "")
+    assert sorted(seen) == sorted(DEVICE_SOURCES)
+    assert "solver.hip" in seen and set(HEADERS) <= set(seen) and "lattice.cpp" not in seen
+
+
+def test_kernel_key():
+    assert bench.kernel_key("void lbm::aa_odd<double, lbm::IndexRIADir, false>(double*, int, lbm::IndexRIADir, "
+                            "lbm::Collision, int)") == "aa_odd<double, IndexRIADir, false>"
+    assert bench.kernel_key("(anonymous namespace)::bench_copy(double const*, double*, long)") == "bench_copy"
+
+
+def _write_csv(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, k, v in rows:
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_traffic_from_scales_by_the_copy_kernel_and_splits_clusters(tmp_path):
+    # spheres-32 has 26,185 fluid nodes: ld = 26,240, and the copy kernel
+    # moves 19 * 8 * ld bytes in and as many out
+    n = 26185
+    ld = (n + 63) // 64 * 64
+    copy_bytes = 19 * 8 * ld
+    odd = "void lbm::aa_odd<double, lbm::IndexRIA, false>(double*, int, lbm::IndexRIA, lbm::Collision, int)"
+    copy = "(anonymous namespace)::bench_copy(double const*, double*, long)"
+    fetch = [(1, odd, 100.0), (2, odd, 110.0), (3, odd, 120.0), (40, odd, 300.0), (41, odd, 310.0),
+             (60, copy, copy_bytes / 2 / 1024)]  # the counter reads half the copy's reads
+    write = [(1, odd, 50.0), (2, odd, 50.0), (3, odd, 50.0), (40, odd, 70.0), (41, odd, 70.0),
+             (60, copy, copy_bytes / 1024)]
+    fc, wc, out = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "traffic.json"
+    _write_csv(fc, "FETCH_SIZE", fetch)
+    _write_csv(wc, "WRITE_SIZE", write)
+    doc = bench.traffic_from(str(fc), str(wc), "spheres-32", "test", out_path=str(out))
+    assert json.load(open(out)) == doc
+    assert doc["scale"]["fetch"] == pytest.approx(2.0) and doc["scale"]["write"] == pytest.approx(1.0)
+    k = doc["kernels"]["aa_odd<double, IndexRIA, false>"]
+    assert k["dispatches"] == 3
+    assert k["fetch_bytes"] == int(110.0 * 1024 * 2) and k["write_bytes"] == int(50.0 * 1024)
+    assert k["hbm_bytes_per_launch"] == int(110.0 * 1024 * 2 + 50.0 * 1024)
+    (later,) = k["later_clusters"]
+    assert later["dispatches"] == 2 and later["fetch_bytes"] == int(305.0 * 1024 * 2)
+    assert "bench_copy" not in doc["kernels"]
+    assert doc["source_digest"] == bench.source_digest()
