@@ -729,6 +729,8 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(odd_bytes),
             "avg_launch_us": round(odd_s * 1e6, 2),
+            # the counter-measured bytes (traffic) per launch over the same duration
+            "traffic_GBs": round(traffic / odd_s / 1e9, 1) if traffic else None,
         },
         "hbm_roofline_mflups": {
             "loop_balance_B_per_FLUP": aa["loop_balance_B_per_FLUP"],
