@@ -219,6 +219,20 @@ typedef struct lbm_solver lbm_solver;
 int lbm_solver_workspace_bytes(const lbm_params* p, int64_t* bytes);
 
 /*
+ * Device bytes a caller allocates for a solver with parameters p (host,
+ * touches no device): *pdf_bytes_per_grid = 19 * ldf * (8, 4 or 2 bytes per
+ * stored PDF of LBM_F64, LBM_F32, LBM_F16), the size of one PDF grid
+ * (Sect. 4: 19 PDFs per fluid node; one grid for the AA pattern, two for
+ * OS-NT), and *workspace_bytes as lbm_solver_workspace_bytes. Only
+ * precision, n_fluid and ldf are read; ldf = 0 asks for the smallest valid
+ * stride, N rounded up to a multiple of 64 (at least 64). The index tables
+ * are sized by the lattice (lbm_lattice_sizes, lbm_lattice_direction_runs).
+ * Errors: LBM_EINVAL (null pointer, unknown precision, n_fluid < 0, ldf < N
+ * or not a multiple of 64), LBM_ERANGE (N or 19 * ldf beyond 2^31 - 1).
+ */
+int lbm_required_bytes(const lbm_params* p, int64_t* pdf_bytes_per_grid, int64_t* workspace_bytes);
+
+/*
  * Create a solver over caller-owned device buffers (borrowed, not copied).
  * workspace: device, at least lbm_solver_workspace_bytes. hip_stream: the
  * hipStream_t all work is queued on (NULL: the default stream). The solver
@@ -259,7 +273,9 @@ int lbm_solver_time(const lbm_solver* s, int64_t* t);
  * Macroscopic fields of the pre-collision PDFs f(t): rho[n] and
  * u[a*N + n] = j_a / rho (device double, either may be NULL), and totals
  * (device double[4]: mass, jx, jy, jz summed over all nodes in a fixed
- * order; may be NULL). Synchronises the stream.
+ * order; may be NULL). Synchronises the stream. The totals are always
+ * formed (in the workspace) and checked on the host: LBM_ERANGE if one is
+ * NaN or infinite, i.e. some PDF is (the outputs are still written).
  */
 int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals);
 

@@ -350,6 +350,10 @@ void build_direction_runs(lbm_lattice* L) {
 
 extern "C" {
 
+// The message of the last failing call of any part of the library on this
+// thread (the solver's calls set it too).
+const char* lbm_last_error(void) { return error_buffer(); }
+
 int lbm_lattice_build(const uint8_t* solid, int32_t nx, int32_t ny, int32_t nz,
                       uint32_t periodic_mask, int32_t order, int32_t block, lbm_lattice** out) {
   clear_error();

@@ -88,7 +88,6 @@ int main(int argc, char** argv) {
   const int index = kIndexIds[pick(argv[9], kIndex, 3, "unknown index source")];
   static const char* const kPrec[] = {"f64", "f32", "f16"};
   static const int kPrecIds[] = {LBM_F64, LBM_F32, LBM_F16};
-  static const size_t kPrecBytes[] = {8, 4, 2};
   const int prec_i = pick(argv[10], kPrec, 3, "unknown precision");
   const double tau = std::atof(argv[11]);
   const double force[3] = {std::atof(argv[12]), std::atof(argv[13]), std::atof(argv[14])};
@@ -126,9 +125,11 @@ int main(int argc, char** argv) {
   p.f16_scale_log2 = 10;
   p.collision = LBM_BGK;
 
+  // grid and workspace sizes as the library states them
+  int64_t grid_bytes = 0, ws_bytes = 0;
+  check(lbm_required_bytes(&p, &grid_bytes, &ws_bytes), "required bytes");
   DeviceBuffer grid[2], adj, delta, bits, base, ws, f_dev, tot_dev;
-  const size_t grid_bytes = (size_t)(19 * p.ldf) * kPrecBytes[prec_i];
-  grid[0].alloc(grid_bytes, "grid allocation");
+  grid[0].alloc((size_t)grid_bytes, "grid allocation");
   if (pattern == LBM_PATTERN_OSNT) grid[1].alloc(grid_bytes, "grid allocation");
 
   int64_t runs_used = 0;
@@ -170,8 +171,6 @@ int main(int argc, char** argv) {
   b.head_bits = (const uint64_t*)bits.p;
   b.run_base = (const int32_t*)base.p;
 
-  int64_t ws_bytes = 0;
-  check(lbm_solver_workspace_bytes(&p, &ws_bytes), "workspace size");
   ws.alloc((size_t)ws_bytes, "workspace allocation");
   hipStream_t stream = nullptr;
   check_hip(hipStreamCreate(&stream), "stream");

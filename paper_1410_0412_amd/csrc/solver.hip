@@ -491,13 +491,26 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
 
 extern "C" {
 
-const char* lbm_last_error(void) { return error_buffer(); }
-
 int lbm_solver_workspace_bytes(const lbm_params* p, int64_t* bytes) {
   clear_error();
   if (!p || !bytes) return fail(LBM_EINVAL, "null pointer");
   *bytes = ((int64_t)kRedBlocks * 4 + 4) * sizeof(double);
   return LBM_OK;
+}
+
+int lbm_required_bytes(const lbm_params* p, int64_t* pdf_bytes_per_grid, int64_t* workspace_bytes) {
+  clear_error();
+  if (!p || !pdf_bytes_per_grid || !workspace_bytes) return fail(LBM_EINVAL, "null pointer");
+  if (p->precision != LBM_F64 && p->precision != LBM_F32 && p->precision != LBM_F16)
+    return fail(LBM_EINVAL, "unknown precision %d", p->precision);
+  if (p->n_fluid < 0) return fail(LBM_EINVAL, "n_fluid < 0");
+  if (p->n_fluid > INT32_MAX - 64) return fail(LBM_ERANGE, "n_fluid exceeds the int32 node index");
+  const int64_t ldf = p->ldf == 0 ? (std::max<int64_t>(p->n_fluid, 1) + 63) / 64 * 64 : p->ldf;
+  if (ldf < p->n_fluid || ldf % 64 != 0) return fail(LBM_EINVAL, "ldf must be 0, or >= N and a multiple of 64");
+  if (ldf > (int64_t)INT32_MAX / Q) return fail(LBM_ERANGE, "19 * ldf exceeds the int32 slot index");
+  const int64_t elem = p->precision == LBM_F64 ? 8 : (p->precision == LBM_F32 ? 4 : 2);
+  *pdf_bytes_per_grid = Q * ldf * elem;
+  return lbm_solver_workspace_bytes(p, workspace_bytes);
 }
 
 int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace,
@@ -579,9 +592,12 @@ int lbm_solver_time(const lbm_solver* s, int64_t* t) {
   return LBM_OK;
 }
 
-int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals) {
-  clear_error();
-  if (!s) return fail(LBM_EINVAL, "null solver");
+namespace {
+// The moments kernels with their partial sums in ws (kRedBlocks * 4 + 4
+// doubles): per-block partials, then the four totals at ws + 4 * kRedBlocks,
+// copied to totals if given. Synchronises the stream and checks that the
+// totals are finite.
+int moments_into(lbm_solver* s, double* ws, double* rho, double* u, double* totals) {
   const int32_t N = (int32_t)s->p.n_fluid;
   unsigned parts = 0;
   if (N > 0) {
@@ -590,15 +606,32 @@ int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals) {
     dispatch(s, current_grid(s), [&](auto* F, auto idx) {
       using S = std::remove_pointer_t<decltype(F)>;
       hipLaunchKernelGGL((moments<S, decltype(idx)>), dim3(parts), dim3(kBlock), 0, s->stream, (const S*)F,
-                         N, idx, layout, s->c, rho, u, s->ws);
+                         N, idx, layout, s->c, rho, u, ws);
     });
   }
-  if (totals)  // with no partials the finishing kernel writes zeros
-    hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, s->ws, (int)parts, totals);
+  // with no partials the finishing kernel writes zeros
+  double* sums = ws + 4 * kRedBlocks;
+  hipLaunchKernelGGL(finish_totals, dim3(1), dim3(kBlock), 0, s->stream, ws, (int)parts, sums);
+  if (totals && hipMemcpyAsync(totals, sums, 4 * sizeof(double), hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
+    return device_status("moments (copy)");
+  double host[4] = {0.0, 0.0, 0.0, 0.0};
+  if (hipMemcpyAsync(host, sums, sizeof host, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+    return device_status("moments (copy)");
   int rc = device_status("moments");
   if (rc) return rc;
   if (hipStreamSynchronize(s->stream) != hipSuccess) return device_status("moments (sync)");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(host[k]))
+      return fail(LBM_ERANGE, "non-finite %s total at t = %lld: the PDFs hold NaN or Inf",
+                  k == 0 ? "mass" : "momentum", (long long)s->t);
   return LBM_OK;
+}
+}  // namespace
+
+int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals) {
+  clear_error();
+  if (!s) return fail(LBM_EINVAL, "null solver");
+  return moments_into(s, s->ws, rho, u, totals);
 }
 
 int lbm_solver_export_pdfs(lbm_solver* s, double* f) {

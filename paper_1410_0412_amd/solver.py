@@ -39,6 +39,26 @@ def aligned_empty(torch, numel, dtype, device, align=_GRID_ALIGN):
     return base[off:off + numel]
 
 
+def required_bytes(params):
+    """(PDF bytes per grid, workspace bytes) of a solver with these
+    parameters, as the library sizes them (``lbm_required_bytes``)."""
+    grid, ws = ctypes.c_int64(), ctypes.c_int64()
+    _capi.check(_capi.lib().lbm_required_bytes(ctypes.byref(params), ctypes.byref(grid), ctypes.byref(ws)))
+    return grid.value, ws.value
+
+
+def check_device_tensor(torch, t, name, dtype, numel, device):
+    """ValueError unless ``t`` is a contiguous ``dtype`` tensor of at least
+    ``numel`` elements on ``device``: a kernel reads or writes that many."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if t.dtype != dtype or t.device != device or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError("%s must be a contiguous %s tensor of at least %d elements on %s (got %s, %d elements "
+                         "on %s%s)" % (name, str(dtype).replace("torch.", ""), numel, device,
+                                       str(t.dtype).replace("torch.", ""), t.numel(), t.device,
+                                       "" if t.is_contiguous() else ", not contiguous"))
+
+
 def choose_index(lattice, pattern="aa", precision="f64", margin=0.0, ratio=0.7):
     """Index source for ``ria="auto"``: per-direction runs when they need at
     most ``ratio`` times the index bytes of the paper's runs (and save more
@@ -113,7 +133,12 @@ class Solver:
         ngrids = 2 if pattern == "osnt" else 1
         dev = self.device
         with torch.cuda.device(dev):
-            self.pdf = [aligned_empty(torch, 19 * self.ldf, dtype, dev) for _ in range(ngrids)]
+            sizing = _capi.Params()
+            sizing.precision = _capi.PRECISIONS[precision]
+            sizing.n_fluid, sizing.ldf = N, self.ldf
+            grid_bytes, ws_bytes = required_bytes(sizing)
+            numel = grid_bytes // torch.empty((), dtype=dtype).element_size()
+            self.pdf = [aligned_empty(torch, numel, dtype, dev) for _ in range(ngrids)]
             self.adj = self.run_delta = self.head_bits = self.run_base = None
             self.solid_frac = torch.zeros(max(N, 1), dtype=torch.float64, device=dev) if pbb else None
             lda = ldr = 0
@@ -156,9 +181,7 @@ class Solver:
             b.solid_frac = self.solid_frac.data_ptr() if pbb else None
             self._buffers = b
             L = _capi.lib()
-            nbytes = ctypes.c_int64()
-            _capi.check(L.lbm_solver_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)))
-            self.workspace = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=dev)
+            self.workspace = torch.empty(max(ws_bytes, 8), dtype=torch.uint8, device=dev)
             h = ctypes.c_void_p()
             _capi.check(L.lbm_solver_create(ctypes.byref(p), ctypes.byref(b),
                                             _vp(self.workspace), self.workspace.numel(),
@@ -242,6 +265,9 @@ class Solver:
         return out
 
     def adjoint_seed(self, weight, axis, t, lam):
+        """lam (a float64 grid like ``pdf[0]``) = dJ/df(t) of J = sum_n
+        weight[n] j_axis(n, t)."""
+        check_device_tensor(self.torch, lam, "lam", self.torch.float64, 19 * self.ldf, self.device)
         w = self._dev(weight, (self.n_fluid,))
         self._call(_capi.lib().lbm_adjoint_seed_momentum, _vp(w), int(axis), int(t), _vp(lam))
         self._keep = (w,)
@@ -250,14 +276,18 @@ class Solver:
         """One AA step that also writes the PDFs f(t) it reads into ``save``
         (a float64 grid like ``pdf[0]``): the forward state
         :meth:`adjoint_step` needs for step t. AA, FP64 and BGK only."""
-        torch = self.torch
-        if save.dtype != torch.float64 or save.device != self.device or save.numel() < 19 * self.ldf \
-                or not save.is_contiguous():
-            raise ValueError("save must be a contiguous float64 tensor of %d elements on %s" % (19 * self.ldf,
-                                                                                               self.device))
+        check_device_tensor(self.torch, save, "save", self.torch.float64, 19 * self.ldf, self.device)
         self._call(_capi.lib().lbm_solver_step_save, _vp(save))
 
     def adjoint_step(self, fwd, t, lam, grad):
+        """Backward through the step t -> t+1: ``fwd`` holds f(t) (a grid
+        like ``pdf[0]``), ``lam`` dJ/df(t+1) on entry and dJ/df(t) on exit,
+        ``grad`` (N float64, or None) accumulates dJ/dns."""
+        torch = self.torch
+        check_device_tensor(torch, fwd, "fwd", torch.float64, 19 * self.ldf, self.device)
+        check_device_tensor(torch, lam, "lam", torch.float64, 19 * self.ldf, self.device)
+        if grad is not None:
+            check_device_tensor(torch, grad, "grad", torch.float64, self.n_fluid, self.device)
         self._call(_capi.lib().lbm_adjoint_step, _vp(fwd), int(t), _vp(lam), _vp(grad))
 
     def import_pdfs(self, f, t=0):

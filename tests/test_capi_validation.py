@@ -144,3 +144,64 @@ def test_driver_rejects_bad_arguments(tmp_path):
         args[pos] = bad
         r = run(*args)
         assert r.returncode == 1 and msg in r.stderr, (bad, r.stderr)
+
+
+def required(p):
+    grid, ws = ctypes.c_int64(), ctypes.c_int64()
+    rc = L.lbm_required_bytes(ctypes.byref(p), ctypes.byref(grid), ctypes.byref(ws))
+    return rc, grid.value, ws.value
+
+
+@pytest.mark.parametrize("prec,size", [(0, 8), (1, 4), (2, 2)])
+def test_required_bytes_per_grid(prec, size):
+    # one grid holds 19 PDFs per node slot (Sect. 4) in the storage type
+    need = ctypes.c_int64()
+    assert L.lbm_solver_workspace_bytes(ctypes.byref(params()), ctypes.byref(need)) == 0
+    assert required(params(precision=prec, n_fluid=100, ldf=128)) == (0, 19 * 128 * size, need.value)
+    # ldf = 0: the smallest valid stride, N rounded up to 64
+    assert required(params(precision=prec, n_fluid=100, ldf=0)) == (0, 19 * 128 * size, need.value)
+    assert required(params(precision=prec, n_fluid=128, ldf=0))[1] == 19 * 128 * size
+    assert required(params(precision=prec, n_fluid=0, ldf=0))[1] == 19 * 64 * size
+    # the largest stride the 32-bit slot offsets allow
+    top = (2 ** 31 - 1) // 19 // 64 * 64
+    assert required(params(precision=prec, n_fluid=top, ldf=top))[1] == 19 * top * size
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(precision=3), capi.LBM_EINVAL),
+    (dict(n_fluid=-1, ldf=0), capi.LBM_EINVAL),
+    (dict(n_fluid=100, ldf=96), capi.LBM_EINVAL),
+    (dict(n_fluid=100, ldf=130), capi.LBM_EINVAL),
+    (dict(n_fluid=2 ** 31, ldf=0), capi.LBM_ERANGE),
+    (dict(n_fluid=100, ldf=(2 ** 31 - 1) // 19 // 64 * 64 + 64), capi.LBM_ERANGE),
+])
+def test_required_bytes_rejects(kw, code):
+    assert required(params(**kw))[0] == code
+    assert L.lbm_last_error()
+
+
+def test_required_bytes_null_pointers():
+    out = ctypes.c_int64()
+    assert L.lbm_required_bytes(None, ctypes.byref(out), ctypes.byref(out)) == capi.LBM_EINVAL
+    assert L.lbm_required_bytes(ctypes.byref(params()), None, ctypes.byref(out)) == capi.LBM_EINVAL
+    assert L.lbm_required_bytes(ctypes.byref(params()), ctypes.byref(out), None) == capi.LBM_EINVAL
+
+
+def test_adjoint_argument_checks():
+    # the binding refuses tensors the adjoint kernels would read or write out
+    # of bounds, before any call reaches the device
+    torch = pytest.importorskip("torch")
+    from paper_1410_0412_amd.solver import check_device_tensor
+
+    cpu = torch.device("cpu")
+    ok = torch.zeros(19 * 128, dtype=torch.float64)
+    check_device_tensor(torch, ok, "lam", torch.float64, 19 * 128, cpu)
+    bad = [ok.float(),                                  # FP32
+           ok[: 19 * 128 - 1],                          # one element short
+           torch.zeros(2 * 19 * 128, dtype=torch.float64)[::2],  # strided view
+           None]
+    for t in bad:
+        with pytest.raises(ValueError):
+            check_device_tensor(torch, t, "lam", torch.float64, 19 * 128, cpu)
+    with pytest.raises(ValueError):  # wrong device
+        check_device_tensor(torch, ok, "lam", torch.float64, 19 * 128, torch.device("cuda", 0))
