@@ -2,14 +2,16 @@
 
 One benchmark step is one full AA cycle of AA-RIA in FP64: the direct even
 time step followed by the indirect odd time step (two lattice updates of every
-fluid node), on the 512x128x128 sphere pack at porosity 0.40 (radius-8
-spheres, LS enumeration with blocking factor 64, tau = 0.6). Lattice tables
-and PDFs are resident in HBM before timing starts.
+fluid node), on the 384^3 foam (smoothed Gaussian noise thresholded to
+porosity 0.85, 48.1M fluid nodes, lexicographic order without blocking,
+tau = 0.7). Lattice tables and PDFs are resident in HBM before timing starts.
+Each variant is timed as the median of 5 runs of ``--steps`` cycles.
 
-Also reported: the other propagation variants (AA-IA, OS-NT-IA, OS-NT-RIA),
-GPU analogues of the paper's bandwidth micro-benchmarks (Sect. 5.2, Table 3),
-per-kernel durations from HIP events, the loop-balance Roofline (Sect. 4,
-Sect. 5.2) and the oracle timed on the host CPU.
+Also reported: FP32 AA-RIA on the same lattice, the other propagation
+variants (AA-IA, OS-NT-IA, OS-NT-RIA, FP16), AA-RIA on the 512x128x128
+sphere pack, GPU analogues of the paper's bandwidth micro-benchmarks
+(Sect. 5.2, Table 3), per-kernel durations from HIP events, the loop-balance
+Roofline (Sect. 4, Sect. 5.2) and the oracle timed on the host CPU.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -31,7 +33,9 @@ if ROOT not in sys.path:
 
 METRIC = "MFLUP/s and % of HBM roofline (GB/s ÷ B/FLUP), FP64 vs FP32 AA-RIA, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "spherepack-512x128x128"
+WORKLOAD = "foam-384"
+SIDE_WORKLOAD = "spherepack-512x128x128"
+REPEATS = 5  # timed runs per variant of the default line; the median counts
 
 
 def log(*a):
@@ -123,41 +127,60 @@ def kernel_key(name):
     return "".join(out).strip()
 
 
-def traffic_from(fetch_csv, write_csv, workload_name, command, out_path=None):
-    """Write profiles/traffic.json (or out_path) from two rocprofv3 --pmc runs
-    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch). Both counters are scaled by
-    what they read for the copy micro-benchmark, whose bytes are known."""
+def _counter_clusters(path, counters):
+    """Per kernel: the averages of ``counters`` over each cluster of
+    consecutive dispatch ids of one rocprofv3 --pmc csv file. The variants
+    run one after the other, so a kernel shared by two variants (the odd
+    step with and without the XCD remap) shows up as separate clusters; each
+    cluster is averaged on its own."""
     import csv
 
-    def load(path, counter):
-        # per kernel: (dispatch id, bytes) in launch order; the variants run
-        # one after the other, so a kernel shared by two variants (the odd step
-        # with and without the XCD remap) shows up as separate clusters of
-        # dispatch ids; each cluster is averaged on its own
-        acc = {}
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] != counter:
-                continue
-            k = kernel_key(r["Kernel_Name"])
-            acc.setdefault(k, []).append((int(r["Dispatch_Id"]), float(r["Counter_Value"]) * 1024.0))
-        out = {}
-        for k, v in acc.items():
-            v.sort()
-            clusters = [[v[0][1]]]
-            for (d0, _), (d1, b) in zip(v, v[1:]):
-                if d1 - d0 > 4:
-                    clusters.append([])
-                clusters[-1].append(b)
-            out[k] = [(sum(c) / len(c), len(c)) for c in clusters]
-        return out
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] not in counters:
+            continue
+        k = kernel_key(r["Kernel_Name"])
+        acc.setdefault(k, {}).setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = {}
+    for k, per in acc.items():
+        ids = sorted(per)
+        clusters = [[ids[0]]]
+        for d0, d1 in zip(ids, ids[1:]):
+            if d1 - d0 > 4:
+                clusters.append([])
+            clusters[-1].append(d1)
+        out[k] = [({c: sum(per[i].get(c, 0.0) for i in cl) / len(cl) for c in counters}, len(cl))
+                  for cl in clusters]
+    return out
 
-    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+
+def traffic_from(fetch_csv, write_csv, workload_name, command, out_path=None, rdreq_csv=None, wrreq_csv=None):
+    """Write profiles/traffic.json (or out_path) from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch). Both counters are scaled by
+    what they read for the copy micro-benchmark, whose bytes are known.
+
+    With request counts (``rdreq_csv``: TCC_EA0_RDREQ_sum, TCC_EA0_RDREQ_32B_sum,
+    TCC_BUBBLE_sum; ``wrreq_csv``: TCC_EA0_WRREQ_sum, TCC_EA0_WRREQ_64B_sum)
+    the same bytes are also formed from the number and size of the requests
+    the L2 sends to memory, as a check of the scale factors: read requests
+    of 128 B (the copy's bytes over its request count), writes of 64 B or
+    32 B."""
+    fetch = {k: [(v["FETCH_SIZE"] * 1024.0, n) for v, n in cl]
+             for k, cl in _counter_clusters(fetch_csv, ("FETCH_SIZE",)).items()}
+    write = {k: [(v["WRITE_SIZE"] * 1024.0, n) for v, n in cl]
+             for k, cl in _counter_clusters(write_csv, ("WRITE_SIZE",)).items()}
     mask, p = __import__("lbm_inputs").workload(workload_name)
     n = int((mask == 0).sum())
     ld = (n + 63) // 64 * 64
     copy_bytes = 8 * 19 * ld  # read once and written once by the copy kernel
     sf = copy_bytes / fetch["bench_copy"][0][0]
     sw = copy_bytes / write["bench_copy"][0][0]
+    rd = wr = None
+    if rdreq_csv and wrreq_csv:
+        rd = _counter_clusters(rdreq_csv, ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum"))
+        wr = _counter_clusters(wrreq_csv, ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum"))
+        c = rd["bench_copy"][0][0]
+        read_req_bytes = copy_bytes / c["TCC_EA0_RDREQ_sum"]
     kernels = {}
     for k in sorted(set(fetch) & set(write)):
         if k.startswith("bench_") or k.startswith("at::"):
@@ -170,25 +193,88 @@ def traffic_from(fetch_csv, write_csv, workload_name, command, out_path=None):
             kernels[k]["later_clusters"] = [
                 {"fetch_bytes": int(f * sf), "write_bytes": int(w * sw), "dispatches": n}
                 for (f, n), (w, _) in zip(fetch[k][1:], write[k][1:])]
+        if rd is not None and k in rd and k in wr:
+            r, w = rd[k][0][0], wr[k][0][0]
+            kernels[k]["requests"] = {
+                "read": int(r["TCC_EA0_RDREQ_sum"]), "read_32B": int(r["TCC_EA0_RDREQ_32B_sum"]),
+                "read_128B_bubble": int(r["TCC_BUBBLE_sum"]),
+                "write": int(w["TCC_EA0_WRREQ_sum"]), "write_64B": int(w["TCC_EA0_WRREQ_64B_sum"]),
+                "read_bytes": int(r["TCC_EA0_RDREQ_32B_sum"] * 32
+                                  + (r["TCC_EA0_RDREQ_sum"] - r["TCC_EA0_RDREQ_32B_sum"]) * read_req_bytes),
+                "write_bytes": int(w["TCC_EA0_WRREQ_64B_sum"] * 64
+                                   + (w["TCC_EA0_WRREQ_sum"] - w["TCC_EA0_WRREQ_64B_sum"]) * 32)}
     doc = {"workload": workload_name, "source_digest": source_digest(),
            "scale": {"fetch": round(sf, 4), "write": round(sw, 4),
                      "reference": "copy micro-benchmark of %d bytes" % copy_bytes},
            "command": command, "kernels": kernels}
+    if rd is not None:
+        doc["request_check"] = {
+            "read_request_bytes": round(read_req_bytes, 3),
+            "note": "bytes per L2-to-memory read request of the copy kernel (its bytes over TCC_EA0_RDREQ_sum); "
+                    "FETCH_SIZE counts a request as 64 B unless TCC_BUBBLE marks it as 128 B, and TCC_BUBBLE "
+                    "reads 0 here, hence the fetch scale of 2"}
     with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(doc, fh, indent=1)
     return doc
 
 
-def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_remap=True, sample_every=16):
-    """Time `steps` cycles of two time steps each, queued back to back.
+def trace_summary(trace_csv):
+    """Per-launch statistics of a rocprofv3 kernel trace (k_kernel_trace.csv),
+    one row per run of consecutive dispatches of one kernel at one grid size
+    (a bench variant on one lattice): calls, mean and minimum duration."""
+    import csv
 
-    Returns (wall seconds, even-step durations, odd-step durations, index).
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
+    groups = []
+    last = {}
+    for r in rows:
+        key = (kernel_key(r["Kernel_Name"]), int(r["Grid_Size_X"]))
+        d = int(r["Dispatch_Id"])
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        g = last.get(key)
+        if g is None or d - g["last"] > 6:
+            g = {"kernel": key[0], "grid": key[1], "first": d, "last": d, "us": []}
+            groups.append(g)
+            last[key] = g
+        g["last"] = d
+        g["us"].append(us)
+    return [{"kernel": g["kernel"], "grid": g["grid"], "first_dispatch": g["first"], "calls": len(g["us"]),
+             "avg_us": round(float(np.mean(g["us"])), 2), "min_us": round(float(np.min(g["us"])), 2)}
+            for g in groups]
+
+
+class Timing:
+    """Timed cycles of one variant: host-clock seconds of each repeat, and
+    HIP-event durations of the first and second step of sampled cycles."""
+
+    def __init__(self, walls, first, second, index):
+        self.walls, self.first, self.second, self.index = walls, first, second, index
+
+    @property
+    def wall(self):
+        """Seconds of all repeats together."""
+        return float(sum(self.walls))
+
+    def median_wall(self):
+        return float(np.median(self.walls))
+
+    # (wall, first, second, index), for callers that time one repeat
+    def __iter__(self):
+        return iter((self.wall, self.first, self.second, self.index))
+
+
+def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_remap=True, sample_every=16,
+                 repeats=1):
+    """Time ``repeats`` runs of ``steps`` cycles of two time steps each, queued
+    back to back, each run bracketed by synchronisations.
+
     Kernel durations come from HIP events on the solver's stream around
-    single launches inside the timed run: the first step of every
+    single launches inside the timed runs: the first step of every
     `sample_every`-th cycle and the second step of the cycle half-way
-    between. Events around every launch would slow the run itself (4 % in
-    FP64 and 7 % in FP32 on the sphere pack); sampled, they cost about
-    0.2 %."""
+    between (with ``sample_every=1``: both steps of every cycle). An event
+    pair adds about 2 us to a run; around every launch that is 4 % of the
+    run on the 3.3M-node sphere pack (steps of 0.2 ms) and under 0.1 % on
+    the 48M-node foam (steps of 2.4-2.9 ms)."""
     from paper_1410_0412_amd import Solver
 
     s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=precision, xcd_remap=xcd_remap)
@@ -199,30 +285,33 @@ def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_rema
     every = max(1, int(sample_every))
     half = every // 2
     pairs = ([], [])  # (start, end) events around first / second steps
-    t0 = time.perf_counter()
-    for i in range(steps):
-        k = i % every
-        sample = (k == 0, k == half if every > 1 else True)
-        if not any(sample):
-            s.step(2)
-            continue
-        for j in (0, 1):
-            if not sample[j]:
-                s.step(1)
+    walls = []
+    for _ in range(max(1, int(repeats))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            k = i % every
+            sample = (k == 0, k == half if every > 1 else True)
+            if not any(sample):
+                s.step(2)
                 continue
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            s.step(1)
-            b.record()
-            pairs[j].append((a, b))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+            for j in (0, 1):
+                if not sample[j]:
+                    s.step(1)
+                    continue
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                s.step(1)
+                b.record()
+                pairs[j].append((a, b))
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
     d = [np.array([a.elapsed_time(b) for a, b in pr]) * 1e-3 for pr in pairs]
     _, _, tot = s.moments()
     if not np.isfinite(tot.cpu().numpy()).all():
         raise RuntimeError("non-finite totals after the timed run")
     del s
-    return wall, d[0], d[1], index
+    return Timing(walls, d[0], d[1], index)
 
 
 def microbench(torch, n_nodes):
@@ -269,20 +358,45 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
-def cpu_baseline(mask, p, steps=6):
+def host_mem_available():
+    """Bytes of host memory the OS reports as available (None if unknown)."""
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024
+    except (OSError, ValueError, IndexError):
+        pass
+    return None
+
+
+def cpu_baseline(mask, p, workload_name, cell_budget=5e7):
+    """The full-array FP64 oracle on the host, on a bounded sample of the
+    workload: about ``cell_budget`` cell updates (one time step of the 384^3
+    foam, six of the 512x128x128 sphere pack), on an x-crop of the box if
+    host memory cannot hold about five full PDF arrays."""
     from oracle import dense
 
     solid = mask.astype(bool)
+    steps = max(1, int(round(cell_budget / solid.size)))
+    crop = ""
+    avail = host_mem_available()
+    plane = 19 * 8 * solid.shape[1] * solid.shape[2]
+    if avail is not None and 5 * plane * solid.shape[0] > avail:
+        nx = max(1, int(avail // (5 * plane)))
+        solid = np.ascontiguousarray(solid[:nx])
+        crop = "; x-crop of %d of %d planes (host memory)" % (nx, mask.shape[0])
     f = dense.initial_state(solid)
     t0 = time.perf_counter()
     for _ in range(steps):
         f = dense.step(f, solid, p["periodic"], p["tau"], p["force"])
     dt = time.perf_counter() - t0
+    del f
     n = int((~solid).sum())
     return {"value": round(n * steps / dt / 1e6, 4), "unit": "MFLUP/s", "cores": 1, "kind": "oracle",
-            "sample": "%d time steps of the full-array FP64 numpy oracle on the same %s lattice "
+            "sample": "%d time step(s) of the full-array FP64 numpy oracle on the %s lattice%s "
                       "(single process, one thread; it updates all %d cells, MFLUP/s counts the %d fluid nodes), "
-                      "%.1f s" % (steps, WORKLOAD, solid.size, n, dt),
+                      "%.1f s" % (steps, workload_name, crop, solid.size, n, dt),
             "host": host_cpu()}
 
 
@@ -563,17 +677,22 @@ def stride_sweep(torch, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500, help="timed AA cycles (2 time steps each)")
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed AA cycles (2 time steps each) per repeat; the default line takes the median of 5")
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD,
-                    help="named synthetic workload (default: the 512x128x128 sphere pack)")
+                    help="named synthetic workload of the default line (default: the 384^3 foam)")
     ap.add_argument("--orders", default=None,
                     help="enumeration sweep instead of the default line, e.g. lex:0,lex:8,morton,hilbert")
     ap.add_argument("--with-ia-osnt", action="store_true",
                     help="with --orders: also time FP64 AA-IA and OS-NT with every index source")
+    ap.add_argument("--trace-summary", default=None, metavar="KERNEL_TRACE_CSV",
+                    help="print per-variant launch statistics of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--traffic-requests", nargs=2, metavar=("RDREQ_CSV", "WRREQ_CSV"),
+                    help="with --traffic-from: request-count counter files for the cross-check")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
@@ -590,8 +709,14 @@ def main():
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32/FP16 deviation storage vs FP64 after --steps time steps on --workload")
     args = ap.parse_args()
+    if args.trace_summary:
+        for row in trace_summary(args.trace_summary):
+            print(json.dumps(row))
+        return
     if args.traffic_from:
-        doc = traffic_from(args.traffic_from[0], args.traffic_from[1], args.workload, args.traffic_command)
+        req = args.traffic_requests or (None, None)
+        doc = traffic_from(args.traffic_from[0], args.traffic_from[1], args.workload, args.traffic_command,
+                           rdreq_csv=req[0], wrreq_csv=req[1])
         print(json.dumps(doc["kernels"], indent=1))
         return
     if args.gpus != 1:
@@ -627,15 +752,65 @@ def main():
         print(json.dumps({"metric": "micro-benchmark GB/s vs node count (2 * 19 * 8 B per node; copy: 2 * 19 * ld * 8 B)",
                           "n_gpus": 1, "data": "synthetic", "sizes": rows}), flush=True)
         return
-    if args.workload != WORKLOAD:
-        print("the default line is defined on %s; use --orders for other workloads" % WORKLOAD, file=sys.stderr)
-        sys.exit(2)
-    log("generating", WORKLOAD)
-    mask, p = workload(WORKLOAD, seed=args.seed)
+    return main_line(torch, args)
+
+
+def time_line(torch, lat, p, pattern, ria, prec, args, remap=True):
+    """One variant of the default line: ``REPEATS`` runs of ``args.steps``
+    cycles; events around every launch on lattices whose steps take
+    milliseconds, around sampled launches on smaller ones."""
+    every = 1 if lat.n_fluid >= 10_000_000 else 16
+    return time_variant(torch, lat, p, pattern, ria, prec, args.steps, args.warmup, remap, sample_every=every,
+                        repeats=REPEATS)
+
+
+def line_row(tm, N, idx_bytes, pattern, prec, steps, workload_name=None):
+    """Rates and Roofline fractions of one timed variant (median repeat)."""
+    med = tm.median_wall()
+    mflups = 2 * N * steps / med / 1e6
+    sb = {"f64": 8, "f32": 4, "f16": 2}[prec]
+    idx = idx_bytes[tm.index]
+    if pattern == "aa":
+        kinds = ("even", "odd")
+        avg = (kernel_bytes("even", N, idx, sb) + kernel_bytes("odd", N, idx, sb)) / 2
+    else:
+        kinds = ("osnt", "osnt_b")
+        avg = kernel_bytes("osnt", N, idx, sb)
+    bl = avg / N
+    rates = sorted(2 * N * steps / w / 1e6 for w in tm.walls)
+    row = {
+        "mflups": round(mflups, 1),
+        "index": tm.index,
+        "repeats_mflups": [round(r, 1) for r in rates],
+        "ms_per_time_step": round(med / (2 * steps) * 1e3, 4),
+        "kernel_us": {kinds[0]: round(float(np.mean(tm.first)) * 1e6, 2),
+                      kinds[1]: round(float(np.mean(tm.second)) * 1e6, 2)},
+        "kernel_samples": [int(len(tm.first)), int(len(tm.second))],
+        "loop_balance_B_per_FLUP": round(bl, 3),
+        "hbm_gbs_model": round(mflups * bl / 1e3, 1),
+        "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4),
+    }
+    if workload_name:
+        row["workload"] = workload_name
+        row["fluid_nodes"] = N
+    return row
+
+
+def main_line(torch, args):
+    """The default line: AA-RIA FP64 (value) and FP32 on ``args.workload``,
+    the other propagation variants beside them, AA-RIA FP64/FP32 on the
+    sphere pack, the matched micro-benchmarks, the dominant kernel's
+    Roofline and the oracle on the host."""
+    from lbm_inputs import workload
+    from paper_1410_0412_amd import Lattice
+
+    name = args.workload
+    log("generating", name)
+    mask, p = workload(name, seed=args.seed)
     t0 = time.perf_counter()
     lat = Lattice(mask, p["periodic"], p["order"], p["block"])
     t_build = time.perf_counter() - t0
-    N, R, W = lat.n_fluid, lat.n_runs, lat.n_waves
+    N, R = lat.n_fluid, lat.n_runs
     r = R / N
     log("lattice N=%d R=%d r=%.4f built in %.2fs" % (N, R, r, t_build))
 
@@ -653,29 +828,10 @@ def main():
     for pattern, ria, prec, remap in variants:
         key = "%s_%s_%s%s" % (pattern, names[ria], prec, "" if remap else "_no_xcd_remap")
         log("timing", key)
-        wall, d_a, d_b, index = time_variant(torch, lat, p, pattern, ria, prec, args.steps, args.warmup, remap)
-        mflups = 2 * N * args.steps / wall / 1e6
-        sb = {"f64": 8, "f32": 4, "f16": 2}[prec]
-        idx = idx_bytes[index]
-        if pattern == "aa":
-            kinds = ("even", "odd")
-            avg = (kernel_bytes("even", N, idx, sb) + kernel_bytes("odd", N, idx, sb)) / 2
-        else:
-            kinds = ("osnt", "osnt_b")
-            avg = kernel_bytes("osnt", N, idx, sb)
-        bl = avg / N
-        res[key] = {
-            "mflups": round(mflups, 1),
-            "index": index,
-            "ms_per_time_step": round(wall / (2 * args.steps) * 1e3, 4),
-            "kernel_us": {kinds[0]: round(float(np.mean(d_a)) * 1e6, 2),
-                          kinds[1]: round(float(np.mean(d_b)) * 1e6, 2)},
-            "loop_balance_B_per_FLUP": round(bl, 3),
-            "hbm_gbs_model": round(mflups * bl / 1e3, 1),
-            "frac_of_hbm_roofline": round(mflups / (HBM_PEAK_GBS * 1e3 / bl), 4),
-        }
+        tm = time_line(torch, lat, p, pattern, ria, prec, args, remap)
+        res[key] = line_row(tm, N, idx_bytes, pattern, prec, args.steps)
         if key == "aa_ria_f64":
-            main_wall, main_odd, main_index = wall, d_b, index
+            main_tm = tm
         log(key, res[key])
 
     micro = microbench(torch, N)
@@ -687,12 +843,29 @@ def main():
         bw = micro["U-19T" if key.startswith("aa") else "CNT-19T"]
         row["frac_of_matched_roofline"] = round(row["mflups"] / (bw * 1e3 / row["loop_balance_B_per_FLUP"]), 4)
 
+    side = SIDE_WORKLOAD if name != SIDE_WORKLOAD else None
+    if side and not args.no_variants:
+        # the sphere pack (short runs, r = 0.67) beside the foam
+        log("generating", side)
+        smask, sp = workload(side, seed=args.seed)
+        slat = Lattice(smask, sp["periodic"], sp["order"], sp["block"])
+        sib = slat.index_bytes()
+        for prec in ("f64", "f32"):
+            key = "spherepack_aa_ria_" + prec
+            log("timing", key)
+            tm = time_line(torch, slat, sp, "aa", "auto", prec, args)
+            res[key] = line_row(tm, slat.n_fluid, sib, "aa", prec, args.steps, side)
+            log(key, res[key])
+        del slat, smask
+
     aa = res["aa_ria_f64"]
+    main_index = main_tm.index
     odd_bytes = kernel_bytes("odd", N, idx_bytes[main_index])
-    odd_s = float(np.mean(main_odd))
+    odd_s = float(np.mean(main_tm.second))
     achieved = odd_bytes / odd_s / 1e9
     odd_kernel = ODD_KERNEL[main_index]
-    traffic = measured_traffic(odd_kernel, WORKLOAD)
+    traffic = measured_traffic(odd_kernel, name)
+    enum = "lex B=%d" % p["block"] if p["block"] > 1 else "lex (no blocking)"
     out = {
         "metric": METRIC,
         "value": aa["mflups"],
@@ -700,23 +873,26 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(main_wall / args.steps * 1e3, 4),
+        "ms_per_step": round(main_tm.median_wall() / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOAD,
+            "workload": name,
             "variant": "AA-RIA",
             "ria_index": main_index,
             "index_bytes_per_node": {k: round(v, 3) for k, v in idx_bytes.items()},
             "direction_runs": lat.n_direction_runs,
             "step": "one AA cycle: direct even step + indirect odd step (2 time steps)",
+            "timing": "median of %d repeats of `steps` cycles, each between two synchronisations; "
+                      "kernel durations from HIP events on the solver's stream" % REPEATS,
             "fluid_nodes": N, "runs": R, "runs_per_node": round(r, 5),
+            "box": list(mask.shape),
             "porosity": round(float(1.0 - mask.mean()), 5),
             "tau": p["tau"], "force": list(p["force"]),
-            "enumeration": "lex B=%d" % p["block"],
+            "enumeration": enum,
             "lattice_build_s": round(t_build, 3),
         },
         "roofline": {
@@ -729,6 +905,7 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(odd_bytes),
             "avg_launch_us": round(odd_s * 1e6, 2),
+            "launch_samples": int(len(main_tm.second)),
             # the counter-measured bytes (traffic) per launch over the same duration
             "traffic_GBs": round(traffic / odd_s / 1e9, 1) if traffic else None,
         },
@@ -744,17 +921,20 @@ def main():
             "frac_of_paper_model_roofline": round(aa["mflups"] / (HBM_PEAK_GBS * 1e3 / (304 + 38 * r)), 4),
         },
         "fp32": {"value": res["aa_ria_f32"]["mflups"], "unit": "MFLUP/s",
+                 "index": res["aa_ria_f32"]["index"],
                  "frac_of_hbm_roofline": res["aa_ria_f32"]["frac_of_hbm_roofline"],
+                 "frac_of_matched_roofline": res["aa_ria_f32"]["frac_of_matched_roofline"],
                  "loop_balance_B_per_FLUP": res["aa_ria_f32"]["loop_balance_B_per_FLUP"],
+                 "kernel_us": res["aa_ria_f32"]["kernel_us"],
                  "storage": "d_q = f_q - w_q rho0 in FP32, FP32 arithmetic"},
         "variants": res,
         "microbench_GBs": micro,
     }
+    del lat
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(mask, p)
+        out["cpu_baseline"] = cpu_baseline(mask, p, name)
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()

@@ -7,7 +7,12 @@ The forward pass stores the AA grid every ``every`` steps. The backward pass
 walks the segments from last to first: it restores a checkpoint, recomputes
 the segment with steps that also store the state each of them reads, and runs
 the adjoint step over those states in reverse. Device memory:
-ceil(T / every) + every grids.
+ceil(T / every) + every grids, and one more grid while a backward pass runs.
+
+The backward pass uses the solid fraction and weight saved by its own forward
+pass, whatever the solver ran in between (another forward pass with other
+fractions, for instance). It leaves the solver as it found it: grid, time
+step and solid fraction are restored when it returns.
 """
 
 from __future__ import annotations
@@ -37,13 +42,17 @@ class OutletFlux(torch.autograd.Function):
         J = solver.weighted_momentum(weight, axis)
         ctx.solver, ctx.steps, ctx.every, ctx.axis = solver, steps, every, axis
         ctx.ckpts = ckpts
-        ctx.save_for_backward(weight)
+        # the fractions this pass ran with (a copy: the caller may change ns)
+        ctx.save_for_backward(weight, ns.detach().clone())
         return J
 
     @staticmethod
     def backward(ctx, gJ):
-        (weight,) = ctx.saved_tensors
+        weight, ns = ctx.saved_tensors
         s, T, every = ctx.solver, ctx.steps, ctx.every
+        # the solver's state when backward starts, restored at the end
+        keep_pdf, keep_t, keep_ns = s.pdf[0].clone(), s.t, s.solid_frac[: s.n_fluid].clone()
+        s.set_solid_fraction(ns)
         lam = torch.empty_like(s.pdf[0])
         grad = torch.zeros(s.n_fluid, dtype=torch.float64, device=s.device)
         s.adjoint_seed(weight, ctx.axis, T, lam)
@@ -58,6 +67,9 @@ class OutletFlux(torch.autograd.Function):
             for t in range(t1 - 1, t0 - 1, -1):
                 s.adjoint_step(states[t - t0], t, lam, grad)
         ctx.ckpts = None
+        s.pdf[0].copy_(keep_pdf)
+        s.set_time(keep_t)
+        s.set_solid_fraction(keep_ns)
         return grad * gJ, None, None, None, None, None
 
 

@@ -258,6 +258,24 @@ struct Prec<float> {
   __device__ static float from64(int, double d, const Collision&) { return (float)d; }
 };
 
+// double -> binary16 with a single rounding to nearest-even. A plain
+// double -> float -> half chain rounds twice and can land on the wrong side
+// of a half-way point. Here the first rounding, to float, is made
+// round-to-odd (truncate, then set the last bit if anything was cut off):
+// float keeps 13 more significand bits than half, so rounding that result to
+// nearest gives the correctly rounded half of x (Boldo and Melquiond,
+// "Emulation of FMA and correctly rounded sums: proved algorithms using
+// rounding to odd", IEEE Trans. Computers 57(4), 2008).
+__device__ __forceinline__ _Float16 half_from_double(double x) {
+  float f = (float)x;
+  if ((double)f != x && f == f) {  // inexact (x is not NaN)
+    uint32_t b = __float_as_uint(f);
+    if (fabs((double)f) > fabs(x)) b -= 1;  // one step towards zero
+    f = __uint_as_float(b | 1u);
+  }
+  return (_Float16)f;
+}
+
 template <>
 struct Prec<_Float16> {
   static constexpr bool kDeviation = true;
@@ -277,7 +295,7 @@ struct Prec<_Float16> {
     return (double)v * (double)c.h_unscale[q];
   }
   __device__ static _Float16 from64(int q, double d, const Collision& c) {
-    return (_Float16)(float)(d * (double)c.h_scale[q]);
+    return half_from_double(d * (double)c.h_scale[q]);
   }
 };
 

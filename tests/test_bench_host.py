@@ -88,3 +88,35 @@ def test_traffic_from_scales_by_the_copy_kernel_and_splits_clusters(tmp_path):
     assert later["dispatches"] == 2 and later["fetch_bytes"] == int(305.0 * 1024 * 2)
     assert "bench_copy" not in doc["kernels"]
     assert doc["source_digest"] == bench.source_digest()
+
+
+def test_traffic_request_check(tmp_path):
+    # read requests of 128 B (the copy's bytes over its request count),
+    # writes of 64 B and 32 B
+    n = 26185
+    ld = (n + 63) // 64 * 64
+    copy_bytes = 19 * 8 * ld
+    odd = "void lbm::aa_odd<double, lbm::IndexRIADir, false>(double*, int, lbm::IndexRIADir, lbm::Collision, int)"
+    copy = "(anonymous namespace)::bench_copy(double const*, double*, long)"
+    fc, wc = tmp_path / "f.csv", tmp_path / "w.csv"
+    _write_csv(fc, "FETCH_SIZE", [(1, odd, 100.0), (60, copy, copy_bytes / 2 / 1024)])
+    _write_csv(wc, "WRITE_SIZE", [(1, odd, 50.0), (60, copy, copy_bytes / 1024)])
+    rc, wq = tmp_path / "r.csv", tmp_path / "q.csv"
+    with open(rc, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, k, req, r32 in ((1, odd, 1000, 10), (60, copy, copy_bytes // 128, 0)):
+            for c, v in (("TCC_EA0_RDREQ_sum", req), ("TCC_EA0_RDREQ_32B_sum", r32), ("TCC_BUBBLE_sum", 0)):
+                w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+    with open(wq, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, k, req, r64 in ((1, odd, 800, 700), (60, copy, copy_bytes // 64, copy_bytes // 64)):
+            for c, v in (("TCC_EA0_WRREQ_sum", req), ("TCC_EA0_WRREQ_64B_sum", r64)):
+                w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+    doc = bench.traffic_from(str(fc), str(wc), "spheres-32", "test", out_path=str(tmp_path / "t.json"),
+                             rdreq_csv=str(rc), wrreq_csv=str(wq))
+    assert doc["request_check"]["read_request_bytes"] == pytest.approx(128.0)
+    r = doc["kernels"]["aa_odd<double, IndexRIADir, false>"]["requests"]
+    assert r["read_bytes"] == 990 * 128 + 10 * 32
+    assert r["write_bytes"] == 700 * 64 + 100 * 32

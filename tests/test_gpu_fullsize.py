@@ -67,11 +67,19 @@ def test_spherepack_variants_identical_and_conserve_mass(pack):
         assert np.array_equal(r, results[0])
 
 
-@pytest.mark.parametrize("order,block,ria", [("lex", 0, True), ("lex", 8, "direction"), ("morton", 0, True),
-                                             ("hilbert_ls", 8, True)])
-def test_foam384_sampled_sites(order, block, ria):
-    # the 384^3 foam of the enumeration sweep and the precision study
-    mask, p = workload("foam-384", seed=0)
+@pytest.fixture(scope="module")
+def foam():
+    # the 384^3 foam of the benchmark's default line, the enumeration sweep
+    # and the precision study
+    return workload("foam-384", seed=0)
+
+
+@pytest.mark.parametrize("order,block,ria", [("lex", 0, "direction"), ("lex", 0, True), ("lex", 8, "direction"),
+                                             ("morton", 0, True), ("hilbert_ls", 8, True)])
+def test_foam384_sampled_sites(foam, order, block, ria):
+    # ("lex", 0, "direction") is the benchmark's main line: LS without
+    # blocking, per-direction runs (the automatic choice on this lattice)
+    mask, p = foam
     steps = 2
     rho0, u0 = init_fields(mask.shape, seed=21)
     fl = np.flatnonzero(mask.reshape(-1) == 0)
@@ -90,6 +98,34 @@ def test_foam384_sampled_sites(order, block, ria):
     idx = torch.from_numpy(node_of[pick]).cuda()
     got = f[:, idx].T.cpu().numpy()
     assert np.array_equal(got, want)
+
+
+def test_foam384_fp32_against_fp64(foam):
+    # the benchmark's FP32 line (LS without blocking, automatic index choice)
+    # against the FP64 line on the same random state, 20 steps; bounds as for
+    # the sphere pack
+    mask, p = foam
+    steps = 20
+    rho0, u0 = init_fields(mask.shape, seed=23)
+    from paper_1410_0412_amd import Lattice, Solver
+    lat = Lattice(mask, p["periodic"], p["order"], p["block"])
+    r, v = node_fields(lat, rho0, u0)
+    del rho0, u0
+    out = {}
+    for pr in ("f64", "f32"):
+        s = Solver(lat, p["tau"], p["force"], pattern="aa", ria="auto", precision=pr)
+        print("case foam-384 deviation storage", pr, "index", s.index, flush=True)
+        s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+        s.step(steps)
+        rho, u, tot = s.moments()
+        out[pr] = (rho, u, tot[0].item())
+        del s
+        torch.cuda.empty_cache()
+    (r64, u64, m64), (r32, u32, m32) = out["f64"], out["f32"]
+    du = (torch.sqrt(((u32 - u64) ** 2).sum(0)).max() / torch.sqrt((u64 ** 2).sum(0)).max()).item()
+    drho = (r32 - r64).abs().max().item()
+    print("f32 on the foam: normwise u %.3e, max rho %.3e, mass %.3e" % (du, drho, abs(m32 - m64) / m64), flush=True)
+    assert du <= 1e-5 and drho <= 1e-7 and abs(m32 - m64) / m64 <= 1e-6
 
 
 def test_channel_sampled_sites_and_variants():

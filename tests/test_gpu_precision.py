@@ -130,3 +130,33 @@ def test_trt_random_state(prec):
     print("trt random-state %s errors %r" % (prec, e), flush=True)
     for k, tol in TOL[prec].items():
         assert e[k] <= tol, (k, e[k])
+
+
+def test_f16_import_rounds_once():
+    # FP16 storage holds x = (f - w_q rho0) * 2^s / w_q rounded once to the
+    # nearest half (ties to even), as numpy converts float64 to float16. The
+    # inputs sit next to half-way points between two halves, where rounding
+    # first to float and then to half would land on the wrong side for many
+    # of them (about 40 % of these).
+    from paper_1410_0412_amd import Lattice, Solver
+    mask = rsa_spheres((16, 16, 16), 2.5, 0.2, PER, seed=3)
+    lat = Lattice(mask, PER, "lex", 0)
+    N = lat.n_fluid
+    s = Solver(lat, 0.8, (0.0, 0.0, 0.0), precision="f16", f16_scale_log2=10)
+    w = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
+    hs = np.array([2.0 ** 10 * (3 if q == 0 else (18 if q < 7 else 36)) for q in range(19)])
+    rng = np.random.default_rng(5)
+    h = rng.uniform(-2000, 2000, (19, N)).astype(np.float16).astype(np.float64)
+    ulp = np.spacing(np.abs(h).astype(np.float16)).astype(np.float64)
+    x = (np.abs(h) + ulp / 2) * np.sign(h) * (1 + rng.integers(-3, 4, (19, N)) * 2.0 ** -35)
+    f = x / hs[:, None] + w[:, None] * 1.0
+    # the kernel's own double operations, in its order
+    want = ((f - w[:, None] * 1.0) * hs[:, None]).astype(np.float16)
+    twice = ((f - w[:, None] * 1.0) * hs[:, None]).astype(np.float32).astype(np.float16)
+    assert (want.view(np.uint16) != twice.view(np.uint16)).mean() > 0.2  # the case is sensitive
+    s.import_pdfs(torch.from_numpy(f).cuda(), t=0)
+    grid = s.pdf[0].cpu().numpy()
+    n = np.arange(N)
+    slots = (19 * (n // 64))[None, :] * 64 + np.arange(19)[:, None] * 64 + (n % 64)[None, :]
+    got = grid[slots]
+    assert np.array_equal(got.view(np.uint16), want.view(np.uint16))
