@@ -134,35 +134,137 @@ def test_checkpoint_interval_does_not_change_gradient(small):
         assert np.array_equal(g, grads[0])
 
 
-def test_finite_differences_spherepack128():
+def test_backward_uses_its_own_forward_and_restores_the_solver(small):
+    # forward(ns1), forward(ns2), then the backward of the first: the
+    # gradient equals that of forward(ns1) alone, bitwise, and the solver
+    # keeps the grid, time and solid fraction the second forward left
+    from paper_1410_0412_amd import outlet_flux
+    mask, ns, w = small
+    T, every = 12, 5
+    lat, s = solver_for(mask, PER, 0.8, (1e-5, 0, 0), "aa", "direction", pbb=True)
+    wt = torch.from_numpy(nodes_of(lat, w)).cuda()
+    ns1 = torch.from_numpy(nodes_of(lat, ns)).cuda()
+    ns2 = (ns1 * 0.5).flip(0)
+    x_ref = ns1.clone().requires_grad_(True)
+    outlet_flux(x_ref, s, T, every, wt).backward()
+    x1 = ns1.clone().requires_grad_(True)
+    x2 = ns2.clone().requires_grad_(True)
+    J1 = outlet_flux(x1, s, T, every, wt)
+    J2 = outlet_flux(x2, s, T + 1, every, wt)
+    after_pdf, after_t, after_ns = s.pdf[0].clone(), s.t, s.solid_frac[: s.n_fluid].clone()
+    assert after_t == T + 1 and torch.equal(after_ns, ns2)
+    J1.backward()
+    assert torch.equal(x1.grad, x_ref.grad)
+    assert torch.equal(s.pdf[0], after_pdf) and s.t == after_t
+    assert torch.equal(s.solid_frac[: s.n_fluid], after_ns)
+    # the solver steps on from the restored state exactly as before
+    J2.backward()
+    x2_ref = ns2.clone().requires_grad_(True)
+    _, s2 = solver_for(mask, PER, 0.8, (1e-5, 0, 0), "aa", "direction", pbb=True)
+    outlet_flux(x2_ref, s2, T + 1, every, wt).backward()
+    assert torch.equal(x2.grad, x2_ref.grad)
+
+
+def ridders(D, h0, levels=7, c=2.0):
+    """Derivative from central differences D(h) by Ridders' method (C. J. F.
+    Ridders, Adv. Eng. Software 4(2), 1982): a Neville tableau extrapolates
+    D(h0), D(h0/c), D(h0/c^2), ... to h = 0 in powers of h^2; the entry whose
+    neighbours in the tableau agree best is kept, and the sweep stops once
+    the diagonal drifts away by more than twice that agreement. Returns
+    (estimate, error estimate). The estimate uses only values of J."""
+    prev = [D(h0)]
+    best, err = prev[0], float("inf")
+    h = h0
+    for i in range(1, levels):
+        h /= c
+        row = [D(h)]
+        f = c * c
+        for j in range(1, i + 1):
+            row.append((row[j - 1] * f - prev[j - 1]) / (f - 1))
+            f *= c * c
+            e = max(abs(row[j] - row[j - 1]), abs(row[j] - prev[j - 1]))
+            if e <= err:
+                err, best = e, row[j]
+        if abs(row[i] - prev[i - 1]) >= 2 * err:
+            break
+        prev = row
+    return best, err
+
+
+def spherepack128_gradient(force):
     from paper_1410_0412_amd import outlet_flux
     mask, p = workload("spherepack-128", seed=0)
     ns_vox = pbb_fraction(mask, seed=1)
-    w_vox = outlet_weight(mask)
     T, every = p["steps"], 20
-    lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], "aa", True, p["order"], p["block"], pbb=True)
+    lat, s = solver_for(mask, p["periodic"], p["tau"], force, "aa", True, p["order"], p["block"], pbb=True)
     ns = torch.from_numpy(nodes_of(lat, ns_vox)).cuda()
-    w = torch.from_numpy(nodes_of(lat, w_vox)).cuda()
+    w = torch.from_numpy(nodes_of(lat, outlet_weight(mask))).cuda()
     x = ns.clone().requires_grad_(True)
     J = outlet_flux(x, s, T, every, w)
     J.backward()
     g = x.grad.cpu().numpy()
-    print("spherepack-128: N=%d J=%.6e max|g|=%.3e" % (lat.n_fluid, J.item(), np.abs(g).max()), flush=True)
+    print("spherepack-128, F = %g: N=%d J=%.6e max|g|=%.3e" % (force[0], lat.n_fluid, J.item(), np.abs(g).max()),
+          flush=True)
+
+    def fd(i):
+        def Jat(h):
+            y = ns.clone()
+            y[i] += h
+            return outlet_flux(y, s, T, every, w).item()
+
+        def D(h):
+            return (Jat(h) - Jat(-h)) / (2 * h)
+        # J is a polynomial of degree ~T in each ns: steps from 8e-3 down
+        est, _ = ridders(D, 8e-3)
+        return abs(est - g[i]) / abs(g[i])
+
+    return mask, lat, ns_vox, g, fd
+
+
+def test_finite_differences_spherepack128():
+    # the benchmark's adjoint case (F = 1e-6): the 32 largest gradients
+    _, _, _, g, fd = spherepack128_gradient((1e-6, 0.0, 0.0))
     top = np.argsort(-np.abs(g))[:32]
     assert np.abs(g[top]).min() >= 1e-3 * np.abs(g).max()
+    worst = max(fd(int(i)) for i in top)
+    print("finite differences, F = 1e-6: worst relative deviation %.3e over the 32 largest |g|" % worst, flush=True)
+    assert worst <= 1e-6
 
-    def Jat(i, h):
-        y = ns.clone()
-        y[i] += h
-        return outlet_flux(y, s, T, every, w).item()
 
-    # J is a polynomial of degree ~T in each ns, so the step must be small:
-    # Richardson's O(h^4) remainder is ~1e-2 at h = 1e-2 but negligible at
-    # h = 5e-4, where FP64 cancellation stays below 1e-8 relative
-    worst = 0.0
-    for i in top:
-        D = lambda h: (Jat(int(i), h) - Jat(int(i), -h)) / (2 * h)
-        fd = (4 * D(2.5e-4) - D(5e-4)) / 3  # Richardson
-        worst = max(worst, abs(fd - g[i]) / abs(g[i]))
-    print("finite differences: worst relative deviation %.3e over 32 nodes" % worst, flush=True)
+def test_finite_differences_spherepack128_sampled_nodes():
+    # A seeded sample of the nodes with |g| >= 1e-3 max|g| beyond the 32
+    # largest: 8 on the outlet plane (where J is taken), 8 next to the y/z
+    # walls of the box, 8 partial-bounce-back nodes (0 < ns < 1, next to a
+    # sphere) and 8 anywhere; and the 32 largest again. At F = 1e-6 the FP64
+    # rounding of J (about 1e-15 absolute against J = 1.6e-2) puts a floor of
+    # about 1e-5 on the relative accuracy of any finite difference for
+    # gradients near 1e-3 max|g| (Ridders' own error estimate reaches 1e-5
+    # there). At F = 1e-4, J and max|g| are 100.00 times larger (the flow is
+    # nearly linear in F at these speeds) against the same rounding, and the
+    # finite differences resolve about 1e-7 relative.
+    mask, lat, ns_vox, g, fd = spherepack128_gradient((1e-4, 0.0, 0.0))
+    top = np.argsort(-np.abs(g))[:32]
+    nv = lat.node_voxel().astype(np.int64)
+    x, y, z = np.unravel_index(nv, mask.shape)
+    ok = np.abs(g) >= 1e-3 * np.abs(g).max()
+    ok[top] = False
+    nsn = nodes_of(lat, ns_vox)
+    groups = {"outlet plane": ok & (x == mask.shape[0] - 1),
+              "box walls": ok & ((y == 0) | (y == mask.shape[1] - 1) | (z == 0) | (z == mask.shape[2] - 1)),
+              "partial bounce-back": ok & (nsn > 0),
+              "anywhere": ok}
+    rng = np.random.default_rng(7)
+    picked = []
+    for name, sel in groups.items():
+        cand = np.setdiff1d(np.flatnonzero(sel), np.array(picked, dtype=np.int64))
+        assert len(cand) >= 8, name
+        pick = rng.choice(cand, 8, replace=False)
+        picked.extend(int(i) for i in pick)
+        errs = [fd(int(i)) for i in pick]
+        print("finite differences, F = 1e-4, %s: worst relative deviation %.3e over 8 nodes (|g| / max|g| from "
+              "%.1e to %.1e)" % (name, max(errs), np.abs(g[pick]).min() / np.abs(g).max(),
+                                 np.abs(g[pick]).max() / np.abs(g).max()), flush=True)
+        assert max(errs) <= 1e-6, name
+    worst = max(fd(int(i)) for i in top)
+    print("finite differences, F = 1e-4: worst relative deviation %.3e over the 32 largest |g|" % worst, flush=True)
     assert worst <= 1e-6
