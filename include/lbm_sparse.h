@@ -279,6 +279,22 @@ int lbm_solver_time(const lbm_solver* s, int64_t* t);
  */
 int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same as
+ * lbm_solver_moments, but the partial sums go to a scratch array of
+ * (1024 * 4 + 4) doubles (32,800 bytes) that the library keeps in static
+ * device memory, one copy per device, instead of the solver's workspace.
+ * Results are bitwise those of lbm_solver_moments. The call allocates no
+ * device memory (the first call on a device looks up the array's address).
+ * Every call on a device shares that device's array: calls that overlap in
+ * time on one device (other threads, other streams) race and must be
+ * serialised by the caller. Nothing in it needs clearing between calls: a
+ * call writes every partial sum it reads. The partial sums need at most the array's size
+ * for any lattice; LBM_ERANGE otherwise. Synchronises the stream.
+ */
+int lbm_solver_moments_static(lbm_solver* s, double* rho, double* u, double* totals);
+
 /* f(t) in natural order: device double[19*N], f[q*N + n]. Synchronises. */
 int lbm_solver_export_pdfs(lbm_solver* s, double* f);
 

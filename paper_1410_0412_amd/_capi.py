@@ -97,6 +97,7 @@ def lib():
         "lbm_solver_step": (ctypes.c_int, [vp, ctypes.c_int64]),
         "lbm_solver_time": (ctypes.c_int, [vp, c_i64p]),
         "lbm_solver_moments": (ctypes.c_int, [vp, vp, vp, vp]),
+        "lbm_solver_moments_static": (ctypes.c_int, [vp, vp, vp, vp]),
         "lbm_solver_export_pdfs": (ctypes.c_int, [vp, vp]),
         "lbm_solver_import_pdfs": (ctypes.c_int, [vp, vp, ctypes.c_int64]),
         "lbm_solver_free": (None, [vp]),
@@ -120,7 +121,7 @@ EXPORTED = [
     "lbm_last_error", "lbm_lattice_build", "lbm_lattice_sizes", "lbm_lattice_copy_nodes",
     "lbm_lattice_copy_adjacency", "lbm_lattice_copy_runs", "lbm_lattice_copy_wave_tables",
     "lbm_lattice_direction_runs", "lbm_lattice_copy_direction_tables", "lbm_lattice_free", "lbm_solver_workspace_bytes", "lbm_required_bytes", "lbm_solver_create", "lbm_solver_set_stream",
-    "lbm_solver_init_equilibrium", "lbm_solver_step", "lbm_solver_time", "lbm_solver_moments",
+    "lbm_solver_init_equilibrium", "lbm_solver_step", "lbm_solver_time", "lbm_solver_moments", "lbm_solver_moments_static",
     "lbm_solver_export_pdfs", "lbm_solver_import_pdfs", "lbm_solver_free", "lbm_bench_stream",
     "lbm_solver_set_time", "lbm_solver_weighted_momentum", "lbm_adjoint_seed_momentum", "lbm_adjoint_step",
     "lbm_solver_step_save",

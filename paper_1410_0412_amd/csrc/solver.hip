@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -632,6 +633,56 @@ int lbm_solver_moments(lbm_solver* s, double* rho, double* u, double* totals) {
   clear_error();
   if (!s) return fail(LBM_EINVAL, "null solver");
   return moments_into(s, s->ws, rho, u, totals);
+}
+
+}  // extern "C"
+
+namespace {
+// Scratch of lbm_solver_moments_static: the partial sums of the moments
+// kernels (kRedBlocks * 4 doubles) and the four totals, in device memory the
+// library owns. Each device holds its own copy for the life of the process.
+constexpr int kStaticScratchDoubles = kRedBlocks * 4 + 4;
+__device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of the scratch array, looked
+// up once per device (the array's name in host code is not that address).
+int static_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return device_status("moments_static (device)");
+  if (dev >= kMaxDevices) return fail(LBM_ERANGE, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_EDEVICE, "moments_static: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lbm_solver_moments_static(lbm_solver* s, double* rho, double* u, double* totals) {
+  clear_error();
+  if (!s) return fail(LBM_EINVAL, "null solver");
+  // the moments kernels use at most kRedBlocks blocks for any lattice, so
+  // their partial sums always fit; the check guards the constant
+  int64_t need = 0;
+  lbm_solver_workspace_bytes(&s->p, &need);
+  if (need > (int64_t)sizeof(double) * kStaticScratchDoubles)
+    return fail(LBM_ERANGE, "moments_static needs %lld bytes of scratch, the static array holds %lld",
+                (long long)need, (long long)(sizeof(double) * kStaticScratchDoubles));
+  double* ws = nullptr;
+  int rc = static_scratch(&ws);
+  if (rc) return rc;
+  return moments_into(s, ws, rho, u, totals);
 }
 
 int lbm_solver_export_pdfs(lbm_solver* s, double* f) {
