@@ -366,6 +366,10 @@ int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, d
  *        ld >= n rounded up to 64, dst of 19*ld doubles); src unused.
  * kind 6 "CNT-19T": the CNT-19A copy in the tile-major layout, src -> dst
  *        (both 19*ld doubles, ld >= n rounded up to 64).
+ * kind 7 "U-19T-L": U-19T launched as the FP64 AA even step is (XCD-aware
+ *        chunks of 64 workgroups, 2 workgroups per CU).
+ * kind 8 "CNT-19T-L": CNT-19T in the same launch (the fastest of chunks of
+ *        0, 16 or 64 workgroups with 2 or 5 workgroups per CU, or no cap).
  * Asynchronous on hip_stream.
  */
 int lbm_bench_stream(int32_t kind, const double* src, double* dst, int64_t n, int64_t ld,

@@ -244,10 +244,11 @@ bench_u19(double* __restrict__ F, int64_t n, int64_t ld, double s) {
   for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q] * s, F + q * ld + i);
 }
 
-// The same update in the tile-major layout of the PDF grid.
+// The same update in the tile-major layout of the PDF grid, workgroups in
+// plain or chunked XCD-aware tile order (chunk > 0, as the step kernels).
 __global__ void __launch_bounds__(kBlock)
-bench_u19_tiles(double* __restrict__ F, int64_t n, double s) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+bench_u19_tiles(double* __restrict__ F, int64_t n, double s, int chunk) {
+  const int64_t i = tile_index(chunk) * kBlock + threadIdx.x;
   if (i >= n) return;
   double* Fi = F + (i & ~(int64_t)(kTile - 1)) * Q + (i & (kTile - 1));
   double v[Q];
@@ -258,8 +259,8 @@ bench_u19_tiles(double* __restrict__ F, int64_t n, double s) {
 }
 
 __global__ void __launch_bounds__(kBlock)
-bench_cnt19_tiles(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+bench_cnt19_tiles(const double* __restrict__ src, double* __restrict__ dst, int64_t n, int chunk) {
+  const int64_t i = tile_index(chunk) * kBlock + threadIdx.x;
   if (i >= n) return;
   const int64_t o = (i & ~(int64_t)(kTile - 1)) * Q + (i & (kTile - 1));
   double v[Q];
@@ -351,6 +352,17 @@ unsigned lds_for(int per_cu, int per_block, int wgs) {
   if (per_cu <= 0 || per_block <= 0 || wgs <= 0) return 0;
   const int bytes = std::min(per_cu / wgs, per_block);
   return (bytes > 0 && per_cu / bytes == wgs) ? (unsigned)bytes : 0;
+}
+
+// LDS bytes per workgroup that cap a launch on the current device at `wgs`
+// workgroups per CU (0: no cap).
+unsigned lds_for_device(int wgs) {
+  int dev = 0, per_cu = 0, per_block = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 0;
+  return lds_for(per_cu, per_block, wgs);
 }
 
 void init_occupancy(lbm_solver* s) {
@@ -845,13 +857,27 @@ int lbm_bench_stream(int32_t kind, const double* src, double* dst, int64_t n, in
       hipLaunchKernelGGL(bench_u19, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, n, ld, 1.0);
       break;
     case 5:
+    case 7:
       if (!dst || ld < (n + kTile - 1) / kTile * kTile) return fail(LBM_EINVAL, "U-19T needs dst and ld >= n rounded to 64");
-      hipLaunchKernelGGL(bench_u19_tiles, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, n, 1.0);
+      if (kind == 5) {
+        hipLaunchKernelGGL(bench_u19_tiles, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, n, 1.0, 0);
+      } else {  // the FP64 even step's launch
+        const unsigned lds = lds_for_device(kEvenWgsPerCu[LBM_F64]);
+        hipLaunchKernelGGL(bench_u19_tiles, dim3(chunked_grid(grid_for(n), kEvenChunk)), dim3(kBlock), lds, st, dst,
+                           n, 1.0, kEvenChunk);
+      }
       break;
     case 6:
+    case 8:
       if (!src || !dst || ld < (n + kTile - 1) / kTile * kTile)
         return fail(LBM_EINVAL, "CNT-19T needs src, dst and ld >= n rounded to 64");
-      hipLaunchKernelGGL(bench_cnt19_tiles, dim3(grid_for(n)), dim3(kBlock), 0, st, src, dst, n);
+      if (kind == 6) {
+        hipLaunchKernelGGL(bench_cnt19_tiles, dim3(grid_for(n)), dim3(kBlock), 0, st, src, dst, n, 0);
+      } else {  // the streaming launch of the FP64 even step
+        const unsigned lds = lds_for_device(kEvenWgsPerCu[LBM_F64]);
+        hipLaunchKernelGGL(bench_cnt19_tiles, dim3(chunked_grid(grid_for(n), kEvenChunk)), dim3(kBlock), lds, st,
+                           src, dst, n, kEvenChunk);
+      }
       break;
     case 3:
       if (!dst) return fail(LBM_EINVAL, "U-1A needs dst");
