@@ -100,10 +100,40 @@ def test_foam384_sampled_sites(foam, order, block, ria):
     assert np.array_equal(got, want)
 
 
-def test_foam384_fp32_against_fp64(foam):
-    # the benchmark's FP32 line (LS without blocking, automatic index choice)
-    # against the FP64 line on the same random state, 20 steps; bounds as for
-    # the sphere pack
+def test_foam384_variants_identical_and_conserve_mass(foam):
+    # the benchmark's lattice: all six variants (two patterns x three index
+    # sources) give bitwise the same state after 60 steps from a random
+    # state, and conserve mass to 1e-12
+    mask, p = foam
+    steps = 60
+    rho0, u0 = init_fields(mask.shape, seed=27)
+    from paper_1410_0412_amd import Lattice, Solver
+    lat = Lattice(mask, p["periodic"], p["order"], p["block"])
+    r, v = node_fields(lat, rho0, u0)
+    del rho0, u0
+    first = None
+    for pattern, ria in VARIANTS:
+        s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria)
+        print("case foam-384 variants", pattern, s.index, flush=True)
+        s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+        _, _, t0 = s.moments()
+        s.step(steps)
+        _, u, t1 = s.moments()
+        m0, m1 = t0[0].item(), t1[0].item()
+        assert abs(m1 - m0) / m0 < 1e-12, (pattern, ria)
+        if first is None:
+            first = u
+        else:
+            assert torch.equal(u, first), (pattern, ria)
+        del s, u
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec,tol_u,tol_rho", [("f32", 1e-5, 1e-7), ("f16", 5e-3, 5e-5)])
+def test_foam384_deviation_storage_against_fp64(foam, prec, tol_u, tol_rho):
+    # the benchmark's FP32 and FP16 lines (LS without blocking, automatic
+    # index choice) against the FP64 line on the same random state, 20
+    # steps; bounds as for the sphere pack
     mask, p = foam
     steps = 20
     rho0, u0 = init_fields(mask.shape, seed=23)
@@ -112,7 +142,7 @@ def test_foam384_fp32_against_fp64(foam):
     r, v = node_fields(lat, rho0, u0)
     del rho0, u0
     out = {}
-    for pr in ("f64", "f32"):
+    for pr in ("f64", prec):
         s = Solver(lat, p["tau"], p["force"], pattern="aa", ria="auto", precision=pr)
         print("case foam-384 deviation storage", pr, "index", s.index, flush=True)
         s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
@@ -121,11 +151,12 @@ def test_foam384_fp32_against_fp64(foam):
         out[pr] = (rho, u, tot[0].item())
         del s
         torch.cuda.empty_cache()
-    (r64, u64, m64), (r32, u32, m32) = out["f64"], out["f32"]
-    du = (torch.sqrt(((u32 - u64) ** 2).sum(0)).max() / torch.sqrt((u64 ** 2).sum(0)).max()).item()
-    drho = (r32 - r64).abs().max().item()
-    print("f32 on the foam: normwise u %.3e, max rho %.3e, mass %.3e" % (du, drho, abs(m32 - m64) / m64), flush=True)
-    assert du <= 1e-5 and drho <= 1e-7 and abs(m32 - m64) / m64 <= 1e-6
+    (r64, u64, m64), (rl, ul, ml) = out["f64"], out[prec]
+    du = (torch.sqrt(((ul - u64) ** 2).sum(0)).max() / torch.sqrt((u64 ** 2).sum(0)).max()).item()
+    drho = (rl - r64).abs().max().item()
+    print("%s on the foam: normwise u %.3e, max rho %.3e, mass %.3e" % (prec, du, drho, abs(ml - m64) / m64),
+          flush=True)
+    assert du <= tol_u and drho <= tol_rho and abs(ml - m64) / m64 <= 1e-6
 
 
 def test_channel_sampled_sites_and_variants():
