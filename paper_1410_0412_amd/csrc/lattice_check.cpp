@@ -14,6 +14,11 @@
 //    breaks that rule;
 //  * the wave tables and the per-direction tables give back the adjacency
 //    list for every node and direction;
+//  * the AA odd step's slot map (f_q of node n at slot (qbar, a_q(n)) if
+//    that neighbour is fluid, else (q, n)) and the OS-NT pull map ((q,
+//    a_q(n)) or (qbar, n)) are bijections on the 19 N slots: every slot is
+//    read by exactly one (node, direction), so the in-place AA update has no
+//    race and the pull step reads every stored value once;
 //  * invalid arguments return the documented error codes.
 // Usage: lattice_check [channel]   (exit status 0 when every check passes)
 
@@ -107,6 +112,24 @@ void check_lattice(const std::vector<uint8_t>& mask, int nx, int ny, int nz, uin
     }
     for (int q = 1; q < 19; ++q)
       for (int64_t c = N; c < ld; ++c) expect(adj[(size_t)((q - 1) * ld + c)] == -1, "padding columns -1", ctx);
+  }
+
+  // slot maps of the AA odd step and of the pull step: bijections on 19 N slots
+  for (int map = 0; map < 2; ++map) {
+    std::vector<uint8_t> hit((size_t)(19 * N), 0);
+    bool ok = true;
+    for (int64_t n = 0; n < N; ++n) {
+      for (int q = 0; q < 19; ++q) {
+        int64_t slot = n;  // direction 0: the node's own rest slot
+        if (q > 0) {
+          const int32_t a = adj[(size_t)((q - 1) * ld + n)];
+          const int k = map == 0 ? (a >= 0 ? kOpp[q] : q) : (a >= 0 ? q : kOpp[q]);
+          slot = (int64_t)k * N + (a >= 0 ? a : n);
+        }
+        if (slot < 0 || slot >= 19 * N || hit[(size_t)slot]++) ok = false;
+      }
+    }
+    expect(ok, map == 0 ? "AA odd-step slot map is a bijection" : "pull map is a bijection", ctx);
   }
 
   std::vector<int32_t> start((size_t)R + 1);
