@@ -243,6 +243,57 @@ def trace_summary(trace_csv):
             for g in groups]
 
 
+def order_traffic(sweep_json, fetch_csv, write_csv, tcp_csv, scale_fetch=2.0, scale_write=1.0):
+    """Counter traffic of the AA step kernels per enumeration: the GPU form of
+    the in-cache loop balance of Sect. 5.6. The counter files come from
+    rocprofv3 --pmc runs of the same --orders sweep that wrote ``sweep_json``
+    (FETCH_SIZE; WRITE_SIZE; TCP_TCC_READ_REQ_sum and TCP_TCC_WRITE_REQ_sum).
+    The sweep runs, per order, the paper's runs in FP64 and FP32, then
+    per-direction runs in FP64 and FP32, so the k-th cluster of a kernel's
+    dispatches belongs to the k-th variant that runs it. Memory bytes use the
+    FETCH_SIZE and WRITE_SIZE scales of the copy kernel (from
+    profiles/traffic.json); L1-to-L2 request sizes are those that put the
+    FP64 even step of the first order on its algorithmic bytes."""
+    sweep = json.load(open(sweep_json))
+    orders = list(sweep["orders"])
+    N = sweep["orders"][orders[0]]["fluid_nodes"]
+    fetch = _counter_clusters(fetch_csv, ("FETCH_SIZE",))
+    write = _counter_clusters(write_csv, ("WRITE_SIZE",))
+    tcp = _counter_clusters(tcp_csv, ("TCP_TCC_READ_REQ_sum", "TCP_TCC_WRITE_REQ_sum"))
+    ev64 = tcp["aa_even<double, false>"][0][0]
+    rd_req = 38 * 8 * N / 2 / ev64["TCP_TCC_READ_REQ_sum"]
+    wr_req = 38 * 8 * N / 2 / ev64["TCP_TCC_WRITE_REQ_sum"]
+    out = {"workload": sweep["config"]["workload"], "fluid_nodes": N,
+           "l1_to_l2_request_bytes": {"read": round(rd_req, 2), "write": round(wr_req, 2)},
+           "memory_scale": {"fetch": scale_fetch, "write": scale_write}, "orders": {}}
+    for i, spec in enumerate(orders):
+        row = sweep["orders"][spec]
+        ib = row["index_bytes_per_node"]
+        res = {"runs_per_node": row["runs_per_node"], "index_bytes_per_node": ib}
+        for prec, S, s in (("f64", "double", 8), ("f32", "float", 4)):
+            for ria, idx, cl_even in (("runs", "IndexRIA", 2 * i), ("direction", "IndexRIADir", 2 * i + 1)):
+                odd_k = "aa_odd<%s, %s, false>" % (S, idx)
+                even_k = "aa_even<%s, false>" % S
+                alg_odd = 38 * s * N + ib[ria] * N
+                alg_even = 38 * s * N
+                o_mem = (fetch[odd_k][i][0]["FETCH_SIZE"] * scale_fetch
+                         + write[odd_k][i][0]["WRITE_SIZE"] * scale_write) * 1024.0
+                e_mem = (fetch[even_k][cl_even][0]["FETCH_SIZE"] * scale_fetch
+                         + write[even_k][cl_even][0]["WRITE_SIZE"] * scale_write) * 1024.0
+                t = tcp[odd_k][i][0]
+                l1 = t["TCP_TCC_READ_REQ_sum"] * rd_req + t["TCP_TCC_WRITE_REQ_sum"] * wr_req
+                v = row[prec if ria == "runs" else prec + "_direction"]
+                res["%s_%s" % (prec, ria)] = {
+                    "mflups": v["mflups"], "odd_us": v["odd_us"], "even_us": v["even_us"],
+                    "odd_memory_B_per_node": round(o_mem / N, 2), "odd_algorithmic_B_per_node": round(alg_odd / N, 2),
+                    "odd_memory_over_algorithmic": round(o_mem / alg_odd, 4),
+                    "even_memory_over_algorithmic": round(e_mem / alg_even, 4),
+                    "odd_l1_l2_B_per_node": round(l1 / N, 2),
+                    "odd_l1_l2_over_algorithmic": round(l1 / alg_odd, 4)}
+        out["orders"][spec] = res
+    return out
+
+
 class Timing:
     """Timed cycles of one variant: host-clock seconds of each repeat, and
     HIP-event durations of the first and second step of sampled cycles."""
@@ -690,6 +741,8 @@ def main():
                     help="enumeration sweep instead of the default line, e.g. lex:0,lex:8,morton,hilbert")
     ap.add_argument("--with-ia-osnt", action="store_true",
                     help="with --orders: also time FP64 AA-IA and OS-NT with every index source")
+    ap.add_argument("--order-traffic", nargs=4, metavar=("SWEEP_JSON", "FETCH_CSV", "WRITE_CSV", "TCP_CSV"),
+                    help="per-enumeration counter traffic of an --orders sweep (one JSON document) and exit")
     ap.add_argument("--trace-summary", default=None, metavar="KERNEL_TRACE_CSV",
                     help="print per-variant launch statistics of a rocprofv3 kernel trace and exit")
     ap.add_argument("--traffic-requests", nargs=2, metavar=("RDREQ_CSV", "WRREQ_CSV"),
@@ -710,6 +763,9 @@ def main():
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32/FP16 deviation storage vs FP64 after --steps time steps on --workload")
     args = ap.parse_args()
+    if args.order_traffic:
+        print(json.dumps(order_traffic(*args.order_traffic), indent=1))
+        return
     if args.trace_summary:
         for row in trace_summary(args.trace_summary):
             print(json.dumps(row))
