@@ -120,3 +120,58 @@ def test_traffic_request_check(tmp_path):
     r = doc["kernels"]["aa_odd<double, IndexRIADir, false>"]["requests"]
     assert r["read_bytes"] == 990 * 128 + 10 * 32
     assert r["write_bytes"] == 700 * 64 + 100 * 32
+
+
+def test_order_traffic_maps_clusters_to_orders(tmp_path):
+    # two orders; per order the sweep runs the paper's runs in FP64 and FP32,
+    # then per-direction runs in FP64 and FP32; each variant's launches form
+    # one cluster of dispatch ids
+    N = 1000
+    sweep = {"config": {"workload": "test"}, "orders": {}}
+    for o, ib in (("lex:0", {"runs": 10.0, "direction": 6.0}), ("morton", {"runs": 72.0, "direction": 60.0})):
+        sweep["orders"][o] = {"fluid_nodes": N, "runs_per_node": 0.1, "index_bytes_per_node": ib}
+        for k in ("f64", "f32", "f64_direction", "f32_direction"):
+            sweep["orders"][o][k] = {"mflups": 1.0, "odd_us": 2.0, "even_us": 1.0}
+    sj = tmp_path / "sweep.json"
+    sj.write_text(json.dumps(sweep))
+    ev = {8: "void lbm::aa_even<double, false>(double*, int, lbm::Collision, int)",
+          4: "void lbm::aa_even<float, false>(float*, int, lbm::Collision, int)"}
+    od = {(8, "runs"): "void lbm::aa_odd<double, lbm::IndexRIA, false>(double*)",
+          (8, "direction"): "void lbm::aa_odd<double, lbm::IndexRIADir, false>(double*)",
+          (4, "runs"): "void lbm::aa_odd<float, lbm::IndexRIA, false>(float*)",
+          (4, "direction"): "void lbm::aa_odd<float, lbm::IndexRIADir, false>(float*)"}
+    rows = {"FETCH_SIZE": [], "WRITE_SIZE": [], "TCP_TCC_READ_REQ_sum": [], "TCP_TCC_WRITE_REQ_sum": []}
+    d = 1
+    for i, o in enumerate(sweep["orders"]):
+        for ria in ("runs", "direction"):
+            for s in (8, 4):
+                alg_e = 38 * s * N
+                alg_o = alg_e + sweep["orders"][o]["index_bytes_per_node"][ria] * N
+                f = 1.0 + 0.1 * (i + 1)  # the odd step's excess grows with the order index
+                for k in range(3):
+                    for name, ab, x in ((ev[s], alg_e, 1.0), (od[(s, ria)], alg_o, f)):
+                        rows["FETCH_SIZE"].append((d, name, ab / 2 * x / 2 / 1024))
+                        rows["WRITE_SIZE"].append((d, name, ab / 2 * x / 1024))
+                        rows["TCP_TCC_READ_REQ_sum"].append((d, name, ab / 2 * x * 1.5 / 128))
+                        rows["TCP_TCC_WRITE_REQ_sum"].append((d, name, ab / 2 * x * 1.5 / 64))
+                        d += 1
+                d += 10
+    paths = {}
+    for c, r in rows.items():
+        paths[c] = tmp_path / (c + ".csv")
+        _write_csv(paths[c], c, r)
+    tcp = tmp_path / "tcp.csv"
+    with open(tcp, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for c in ("TCP_TCC_READ_REQ_sum", "TCP_TCC_WRITE_REQ_sum"):
+            for dd, k, v in rows[c]:
+                w.writerow({"Dispatch_Id": dd, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+    out = bench.order_traffic(str(sj), str(paths["FETCH_SIZE"]), str(paths["WRITE_SIZE"]), str(tcp))
+    assert out["l1_to_l2_request_bytes"]["read"] == pytest.approx(128 / 1.5, abs=0.01)
+    for i, o in enumerate(("lex:0", "morton")):
+        for key in ("f64_runs", "f64_direction", "f32_runs", "f32_direction"):
+            r = out["orders"][o][key]
+            assert r["odd_memory_over_algorithmic"] == pytest.approx(1.0 + 0.1 * (i + 1), rel=1e-4)
+            assert r["even_memory_over_algorithmic"] == pytest.approx(1.0, rel=1e-4)
+            assert r["odd_l1_l2_over_algorithmic"] == pytest.approx(1.0 + 0.1 * (i + 1), rel=1e-4)
