@@ -100,6 +100,31 @@ def test_foam384_sampled_sites(foam, order, block, ria):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("pattern,steps", [("aa", 20), ("aa", 21), ("osnt", 20)])
+def test_foam384_twenty_steps_sampled_sites(foam, pattern, steps):
+    # the main line's lattice and index (LS without blocking, per-direction
+    # runs) after 20 and 21 steps (AA exports its natural layout after an
+    # even count, its odd-step slots after an odd one): 6 sites against the
+    # oracle's dependency cone (a 43^3 or 45^3 crop each), bitwise
+    mask, p = foam
+    rho0, u0 = init_fields(mask.shape, seed=25)
+    fl = np.flatnonzero(mask.reshape(-1) == 0)
+    pick = fl[np.random.default_rng(26).choice(len(fl), 6, replace=False)]
+    sites = np.stack(np.unravel_index(pick, mask.shape), 1)
+    want = dense.cone_sites(mask.astype(bool), p["periodic"], p["tau"], p["force"], steps, rho0, u0, sites)
+    print("case foam-384", steps, "steps", pattern, flush=True)
+    lat, s = solver_for(mask, p["periodic"], p["tau"], p["force"], pattern, "direction", p["order"], p["block"])
+    r, v = node_fields(lat, rho0, u0)
+    del rho0, u0
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    s.step(steps)
+    f = s.export_pdfs()
+    node_of = np.full(mask.size, -1, np.int64)
+    node_of[lat.node_voxel().astype(np.int64)] = np.arange(lat.n_fluid)
+    got = f[:, torch.from_numpy(node_of[pick]).cuda()].T.cpu().numpy()
+    assert np.array_equal(got, want)
+
+
 def test_foam384_variants_identical_and_conserve_mass(foam):
     # the benchmark's lattice: all six variants (two patterns x three index
     # sources) give bitwise the same state after 60 steps from a random
