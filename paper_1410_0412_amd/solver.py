@@ -241,6 +241,19 @@ class Solver:
         self._call(_capi.lib().lbm_solver_moments, _vp(rho), _vp(u), _vp(tot))
         return rho, u, tot
 
+    def moments_static(self):
+        """As :meth:`moments`, through ``lbm_solver_moments_static``: the
+        reduction's partial sums go to the library's static device scratch
+        array instead of the solver's workspace (for callers that cannot
+        allocate; calls that overlap on one device race)."""
+        torch = self.torch
+        N = self.n_fluid
+        rho = torch.empty(N, dtype=torch.float64, device=self.device)
+        u = torch.empty((3, N), dtype=torch.float64, device=self.device)
+        tot = torch.empty(4, dtype=torch.float64, device=self.device)
+        self._call(_capi.lib().lbm_solver_moments_static, _vp(rho), _vp(u), _vp(tot))
+        return rho, u, tot
+
     def export_pdfs(self):
         """f(t) in natural order, float64 (19, N)."""
         f = self.torch.empty((19, self.n_fluid), dtype=self.torch.float64, device=self.device)

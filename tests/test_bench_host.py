@@ -175,3 +175,12 @@ def test_order_traffic_maps_clusters_to_orders(tmp_path):
             assert r["odd_memory_over_algorithmic"] == pytest.approx(1.0 + 0.1 * (i + 1), rel=1e-4)
             assert r["even_memory_over_algorithmic"] == pytest.approx(1.0, rel=1e-4)
             assert r["odd_l1_l2_over_algorithmic"] == pytest.approx(1.0 + 0.1 * (i + 1), rel=1e-4)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: the solver has no multi-GPU path, and the bench says so
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr

@@ -55,6 +55,15 @@ def test_moments_static_matches_workspace_moments(pattern, prec):
         del s
 
 
+def test_moments_static_binding():
+    # the Python binding's call of the same entry point
+    s = make((16, 16, 16), 9, "aa", "f32")
+    want = s.moments()
+    got = s.moments_static()
+    for a, b in zip(got, want):
+        assert torch.equal(a, b)
+
+
 def test_moments_static_reports_nonfinite_totals():
     from paper_1410_0412_amd import LbmError
     from paper_1410_0412_amd._capi import LBM_ERANGE
