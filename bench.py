@@ -100,18 +100,23 @@ def source_digest(read=None):
 
 
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if the
-    kernel sources have not changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    try:
-        with open(path) as fh:
-            doc = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    e = doc.get("kernels", {}).get(kernel)
-    if not e or doc.get("workload") != workload or doc.get("source_digest") != source_digest():
-        return None
-    return e.get("hbm_bytes_per_launch")
+    """HBM bytes per launch from committed rocprofv3 counter runs
+    (profiles/traffic.json for the default workload, or
+    profiles/traffic_<workload>.json), if the kernel sources have not changed
+    since the counters were taken."""
+    for name in ("traffic.json", "traffic_%s.json" % workload):
+        try:
+            with open(os.path.join(ROOT, "profiles", name)) as fh:
+                doc = json.load(fh)
+        except (OSError, ValueError):
+            continue
+        if doc.get("workload") != workload:
+            continue
+        e = doc.get("kernels", {}).get(kernel)
+        if not e or doc.get("source_digest") != source_digest():
+            return None
+        return e.get("hbm_bytes_per_launch")
+    return None
 
 
 def kernel_key(name):
@@ -750,6 +755,7 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
+    ap.add_argument("--traffic-out", default=None, help="with --traffic-from: write here instead of profiles/traffic.json")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the forward PBB step, the adjoint step and one gradient on the 128^3 sphere pack")
     ap.add_argument("--micro-sizes", default=None,
@@ -773,7 +779,7 @@ def main():
     if args.traffic_from:
         req = args.traffic_requests or (None, None)
         doc = traffic_from(args.traffic_from[0], args.traffic_from[1], args.workload, args.traffic_command,
-                           rdreq_csv=req[0], wrreq_csv=req[1])
+                           out_path=args.traffic_out, rdreq_csv=req[0], wrreq_csv=req[1])
         print(json.dumps(doc["kernels"], indent=1))
         return
     if args.gpus != 1:
