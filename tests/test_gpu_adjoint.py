@@ -191,20 +191,20 @@ def ridders(D, h0, levels=7, c=2.0):
     return best, err
 
 
-def spherepack128_gradient(force):
+def spherepack128_gradient(force, ria):
     from paper_1410_0412_amd import outlet_flux
     mask, p = workload("spherepack-128", seed=0)
     ns_vox = pbb_fraction(mask, seed=1)
     T, every = p["steps"], 20
-    lat, s = solver_for(mask, p["periodic"], p["tau"], force, "aa", True, p["order"], p["block"], pbb=True)
+    lat, s = solver_for(mask, p["periodic"], p["tau"], force, "aa", ria, p["order"], p["block"], pbb=True)
     ns = torch.from_numpy(nodes_of(lat, ns_vox)).cuda()
     w = torch.from_numpy(nodes_of(lat, outlet_weight(mask))).cuda()
     x = ns.clone().requires_grad_(True)
     J = outlet_flux(x, s, T, every, w)
     J.backward()
     g = x.grad.cpu().numpy()
-    print("spherepack-128, F = %g: N=%d J=%.6e max|g|=%.3e" % (force[0], lat.n_fluid, J.item(), np.abs(g).max()),
-          flush=True)
+    print("spherepack-128, F = %g, index %s: N=%d J=%.6e max|g|=%.3e" % (force[0], s.index, lat.n_fluid, J.item(),
+                                                                         np.abs(g).max()), flush=True)
 
     def fd(i):
         def Jat(h):
@@ -221,9 +221,12 @@ def spherepack128_gradient(force):
     return mask, lat, ns_vox, g, fd
 
 
-def test_finite_differences_spherepack128():
-    # the benchmark's adjoint case (F = 1e-6): the 32 largest gradients
-    _, _, _, g, fd = spherepack128_gradient((1e-6, 0.0, 0.0))
+@pytest.mark.parametrize("ria", [True, "direction"])
+def test_finite_differences_spherepack128(ria):
+    # the benchmark's adjoint case (F = 1e-6): the 32 largest gradients, with
+    # the paper's runs and with per-direction runs (the automatic choice on
+    # this lattice)
+    _, _, _, g, fd = spherepack128_gradient((1e-6, 0.0, 0.0), ria)
     top = np.argsort(-np.abs(g))[:32]
     assert np.abs(g[top]).min() >= 1e-3 * np.abs(g).max()
     worst = max(fd(int(i)) for i in top)
@@ -242,7 +245,7 @@ def test_finite_differences_spherepack128_sampled_nodes():
     # there). At F = 1e-4, J and max|g| are 100.00 times larger (the flow is
     # nearly linear in F at these speeds) against the same rounding, and the
     # finite differences resolve about 1e-7 relative.
-    mask, lat, ns_vox, g, fd = spherepack128_gradient((1e-4, 0.0, 0.0))
+    mask, lat, ns_vox, g, fd = spherepack128_gradient((1e-4, 0.0, 0.0), "direction")
     top = np.argsort(-np.abs(g))[:32]
     nv = lat.node_voxel().astype(np.int64)
     x, y, z = np.unravel_index(nv, mask.shape)
