@@ -320,7 +320,7 @@ class Timing:
 
 
 def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_remap=True, sample_every=16,
-                 repeats=1):
+                 repeats=1, trt_magic=None):
     """Time ``repeats`` runs of ``steps`` cycles of two time steps each, queued
     back to back, each run bracketed by synchronisations.
 
@@ -333,7 +333,8 @@ def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_rema
     the 48M-node foam (steps of 2.4-2.9 ms)."""
     from paper_1410_0412_amd import Solver
 
-    s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=precision, xcd_remap=xcd_remap)
+    s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=precision, xcd_remap=xcd_remap,
+               trt_magic=trt_magic)
     index = s.index
     s.init()
     s.step(2 * warmup)
@@ -818,13 +819,13 @@ def main():
     return main_line(torch, args)
 
 
-def time_line(torch, lat, p, pattern, ria, prec, args, remap=True):
+def time_line(torch, lat, p, pattern, ria, prec, args, remap=True, trt_magic=None):
     """One variant of the default line: ``REPEATS`` runs of ``args.steps``
     cycles; events around every launch on lattices whose steps take
     milliseconds, around sampled launches on smaller ones."""
     every = 1 if lat.n_fluid >= 10_000_000 else 16
     return time_variant(torch, lat, p, pattern, ria, prec, args.steps, args.warmup, remap, sample_every=every,
-                        repeats=REPEATS)
+                        repeats=REPEATS, trt_magic=trt_magic)
 
 
 def line_row(tm, N, idx_bytes, pattern, prec, steps, workload_name=None):
@@ -881,17 +882,21 @@ def main_line(torch, args):
     log("index bytes per node and indirect step", {k: round(v, 3) for k, v in idx_bytes.items()})
     # RIA lines use the library's choice between the paper's runs and
     # per-direction runs ("auto"); the paper's runs are also timed on their own
-    variants = [("aa", "auto", "f64", True), ("aa", "auto", "f32", True)]
+    # (pattern, index, storage, XCD-aware tile order, TRT collision)
+    variants = [("aa", "auto", "f64", True, False), ("aa", "auto", "f32", True, False)]
     if not args.no_variants:
-        variants += [("aa", "runs", "f64", True), ("aa", False, "f64", True), ("osnt", False, "f64", True),
-                     ("osnt", "auto", "f64", True), ("osnt", "runs", "f64", True), ("aa", "auto", "f16", True),
-                     ("aa", "auto", "f64", False)]
+        variants += [("aa", "runs", "f64", True, False), ("aa", False, "f64", True, False),
+                     ("osnt", False, "f64", True, False), ("osnt", "auto", "f64", True, False),
+                     ("osnt", "runs", "f64", True, False), ("aa", "auto", "f16", True, False),
+                     ("aa", "auto", "f64", False, False), ("aa", "auto", "f64", True, True),
+                     ("aa", "auto", "f32", True, True)]
     names = {"auto": "ria", "runs": "ria_runs", False: "ia"}
     res = {}
-    for pattern, ria, prec, remap in variants:
-        key = "%s_%s_%s%s" % (pattern, names[ria], prec, "" if remap else "_no_xcd_remap")
+    for pattern, ria, prec, remap, trt in variants:
+        key = "%s_%s_%s%s%s" % (pattern, names[ria], "trt_" if trt else "", prec, "" if remap else "_no_xcd_remap")
         log("timing", key)
-        tm = time_line(torch, lat, p, pattern, ria, prec, args, remap)
+        # the paper's TRT operator with the magic parameter 3/16 (Sect. 2)
+        tm = time_line(torch, lat, p, pattern, ria, prec, args, remap, trt_magic=3.0 / 16.0 if trt else None)
         res[key] = line_row(tm, N, idx_bytes, pattern, prec, args.steps)
         if key == "aa_ria_f64":
             main_tm = tm
