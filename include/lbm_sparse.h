@@ -184,11 +184,15 @@ typedef struct lbm_params {
   int64_t n_fluid;   /* N                                                    */
   int64_t n_runs;    /* R (LBM_INDEX_RUNS) or RD (LBM_INDEX_DIRECTION_RUNS) */
   int64_t ldf;       /* node slots of the grid: >= N, a multiple of 64,
-                        19*ldf <= 2^31 - 1. Grid layout (tile-major SoA):
-                        direction q of node n = 64t + l is element
-                        (19t + q)*64 + l; a grid holds 19*ldf elements.     */
-  int64_t lda;       /* adjacency row stride (>= N), adjacency only          */
-  int64_t ldr;       /* run_delta row stride (>= R), LBM_INDEX_RUNS only     */
+                        <= 2^31. Grid layout (tile-major SoA): direction q
+                        of node n = 64t + l is element (19t + q)*64 + l; a
+                        grid holds 19*ldf elements. Grids of up to 2^31 - 1
+                        elements (N up to 113 M) step with 32-bit element
+                        offsets, larger ones with 64-bit offsets: one FP64
+                        AA grid can fill the whole of a 288 GB device.     */
+  int64_t lda;       /* adjacency row stride (>= N, <= 2^31), adjacency only */
+  int64_t ldr;       /* run_delta row stride (>= R, <= 2^31), LBM_INDEX_RUNS
+                        only                                                 */
   int32_t f16_scale_log2; /* FP16 storage scale exponent s, in [-24, 24]     */
   int32_t collision; /* LBM_BGK, or LBM_TRT (two relaxation times, Sect. 2):
                         f*_q = f_q - w+ (f+_q - feq+_q) - w- (f-_q - feq-_q)
@@ -228,7 +232,7 @@ int lbm_solver_workspace_bytes(const lbm_params* p, int64_t* bytes);
  * stride, N rounded up to a multiple of 64 (at least 64). The index tables
  * are sized by the lattice (lbm_lattice_sizes, lbm_lattice_direction_runs).
  * Errors: LBM_EINVAL (null pointer, unknown precision, n_fluid < 0, ldf < N
- * or not a multiple of 64), LBM_ERANGE (N or 19 * ldf beyond 2^31 - 1).
+ * or not a multiple of 64), LBM_ERANGE (N above 2^31 - 65, ldf above 2^31).
  */
 int lbm_required_bytes(const lbm_params* p, int64_t* pdf_bytes_per_grid, int64_t* workspace_bytes);
 
@@ -239,8 +243,8 @@ int lbm_required_bytes(const lbm_params* p, int64_t* pdf_bytes_per_grid, int64_t
  * starts at t = 0 with undefined PDFs; call an init or import first.
  * Errors: LBM_EINVAL (tau <= 1/2, bad flags, missing buffers, ldf < N or not
  * a multiple of 64, lda < N, ldr < R, per-direction tables with fewer than 18
- * runs), LBM_ERANGE (N >= 2^31, a slot index 19*ldf that does not fit
- * 2^31 - 1 elements, or more than 2^31 - 1 per-direction runs), LBM_ENOMEM.
+ * runs), LBM_ERANGE (N above 2^31 - 65, ldf, lda or ldr above 2^31, or
+ * more than 2^31 - 1 per-direction runs), LBM_ENOMEM.
  * Creation touches no device; the device limits used by the launches are
  * read at the first step.
  */

@@ -234,6 +234,12 @@ WORKLOADS = {
     "foam-384": dict(
         shape=(384, 384, 384), periodic=(True, False, False), tau=0.7,
         force=(1e-6, 0.0, 0.0), order="lex", block=0, steps=500),
+    # the same foam at 512^3 (114 M fluid nodes): its PDF grids hold more
+    # than 2^31 - 1 elements, so the time step addresses them with 64-bit
+    # offsets
+    "foam-512": dict(
+        shape=(512, 512, 512), periodic=(True, False, False), tau=0.7,
+        force=(1e-6, 0.0, 0.0), order="lex", block=0, steps=500),
     # adjoint workload: radius-8 sphere pack at porosity 0.5
     "spherepack-128": dict(
         shape=(128, 128, 128), periodic=(True, False, False), tau=0.8,
@@ -253,7 +259,7 @@ def workload(name: str, seed: int = 0):
         mask = relaxed_spheres(shape, 8.0, 0.40, seed)
     elif name == "spherepack-128":
         mask = relaxed_spheres(shape, 8.0, 0.50, seed)
-    elif name == "foam-384":
+    elif name in ("foam-384", "foam-512"):
         mask = foam(shape, 4.0, 0.85, seed)
     else:
         raise KeyError(name)

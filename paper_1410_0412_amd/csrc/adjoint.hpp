@@ -23,30 +23,31 @@
 
 namespace lbm {
 
-template <class Idx, bool ODD>
-__device__ __forceinline__ void step_slots(int32_t n, const Idx& idx, int32_t (&g)[Q]) {
+template <class Idx, bool ODD, class Off>
+__device__ __forceinline__ void step_slots(int32_t n, const Idx& idx, Off (&g)[Q]) {
   if constexpr (ODD) {
     int32_t a[18];
     idx.get(n, a);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = aa_slot(q, n, a);
+    for (int q = 0; q < Q; ++q) g[q] = aa_slot<Off>(q, n, a);
   } else {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = pdf_slot(q, n);
+    for (int q = 0; q < Q; ++q) g[q] = pdf_slot<Off>(q, n);
   }
 }
 
 // One AA step with partial bounce-back (ns = NULL: every ns is 0). SAVE
 // also writes the PDFs f(t) it reads into `save`, in the grid's slots of
-// time t: the forward state the adjoint of this step reads.
-template <class Idx, bool ODD, bool SAVE>
+// time t: the forward state the adjoint of this step reads. Off is the slot
+// type (kernels.hpp).
+template <class Idx, bool ODD, bool SAVE, class Off>
 __global__ void __launch_bounds__(kBlock)
 aa_step_pbb(double* __restrict__ F, int32_t N, Idx idx, Collision c,
             const double* __restrict__ ns, double* __restrict__ save, int chunk) {
   const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  int32_t g[Q];
+  Off g[Q];
   step_slots<Idx, ODD>(n, idx, g);
   double f[Q], fs[Q];
 #pragma unroll
@@ -61,14 +62,14 @@ aa_step_pbb(double* __restrict__ F, int32_t N, Idx idx, Collision c,
   for (int q = 0; q < Q; ++q) F[g[kOpp[q]]] = ((1.0 - s) * fs[q]) + (s * f[kOpp[q]]);
 }
 
-template <class Idx, bool ODD>
+template <class Idx, bool ODD, class Off>
 __global__ void __launch_bounds__(kBlock)
 aa_adjoint(const double* __restrict__ F, double* __restrict__ Lam, int32_t N, Idx idx,
            Collision c, const double* __restrict__ ns, double* __restrict__ grad, int chunk) {
   const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  int32_t g[Q];
+  Off g[Q];
   step_slots<Idx, ODD>(n, idx, g);
   double f[Q], mu[Q];
 #pragma unroll
@@ -110,7 +111,7 @@ adjoint_seed(double* __restrict__ Lam, int32_t N, Idx idx, const double* __restr
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  int32_t g[Q];
+  int64_t g[Q];
   step_slots<Idx, ODD>(n, idx, g);
   const double wn = w[n];
 #pragma unroll

@@ -56,7 +56,7 @@ __device__ __forceinline__ int64_t tile_index(int chunk) {
 
 struct IndexIA {
   const int32_t* __restrict__ adj;
-  int32_t lda;
+  int64_t lda;  // 18 * lda may exceed 2^31
 
   __device__ __forceinline__ void get(int32_t n, int32_t (&a)[18]) const {
 #pragma unroll
@@ -68,7 +68,7 @@ struct IndexRIA {
   const int32_t* __restrict__ delta;
   const uint64_t* __restrict__ head_bits;
   const int32_t* __restrict__ run_base;
-  int32_t ldr;
+  int64_t ldr;  // 18 * ldr may exceed 2^31
 
   __device__ __forceinline__ void get(int32_t n, int32_t (&a)[18]) const {
     // all lanes of the wave hold nodes 64w .. 64w+63
@@ -125,49 +125,56 @@ struct IndexRIADir {
   }
 };
 
-// Slots are 32-bit element offsets into the grid (the host guarantees
-// 19 * ldf < 2^31 elements). Per lane a slot costs a compare, two selects
-// and a few integer operations, with no branch.
+// Slots are element offsets into the grid, of type Off: int32_t while the
+// grid holds at most 2^31 - 1 elements (19 * ldf, lattices of up to
+// 113 M nodes), int64_t beyond. The 32-bit form keeps the 19 slots the odd
+// step holds across the collision in 19 registers; 64-bit slots take two
+// each. Node indices stay 32-bit (N < 2^31). Per lane a slot costs a
+// compare, two selects and a few integer operations, with no branch.
 constexpr int32_t kTile = 64;
 
 // Offset of direction 0 of node m; direction q lies q * 64 elements further.
-__device__ __forceinline__ int32_t node_base(int32_t m) {
-  return (m & ~(kTile - 1)) * Q + (m & (kTile - 1));
+template <class Off = int32_t>
+__device__ __forceinline__ Off node_base(int32_t m) {
+  return (Off)(m & ~(kTile - 1)) * Q + (m & (kTile - 1));
 }
 
-__device__ __forceinline__ int32_t pdf_slot(int q, int32_t m) { return node_base(m) + q * kTile; }
+template <class Off = int32_t>
+__device__ __forceinline__ Off pdf_slot(int q, int32_t m) { return node_base<Off>(m) + q * kTile; }
 
 // AA odd-step slot of f_q for node n: L_q(n) = (qbar at a_q(n)) or (q at n).
-__device__ __forceinline__ int32_t aa_slot(int q, int32_t n, const int32_t (&a)[18]) {
-  if (q == 0) return node_base(n);
+template <class Off = int32_t>
+__device__ __forceinline__ Off aa_slot(int q, int32_t n, const int32_t (&a)[18]) {
+  if (q == 0) return node_base<Off>(n);
   const int32_t an = a[q - 1];
   const bool fluid = an >= 0;
   const int32_t m = fluid ? an : n;
-  return node_base(m) + (fluid ? kOpp[q] : q) * kTile;
+  return node_base<Off>(m) + (fluid ? kOpp[q] : q) * kTile;
 }
 
 // OS-NT pull slot of f_q for node n: (q at a_q(n)) or (qbar at n).
-__device__ __forceinline__ int32_t pull_slot(int q, int32_t n, const int32_t (&a)[18]) {
-  if (q == 0) return node_base(n);
+template <class Off = int32_t>
+__device__ __forceinline__ Off pull_slot(int q, int32_t n, const int32_t (&a)[18]) {
+  if (q == 0) return node_base<Off>(n);
   const int32_t an = a[q - 1];
   const bool fluid = an >= 0;
   const int32_t m = fluid ? an : n;
-  return node_base(m) + (fluid ? q : kOpp[q]) * kTile;
+  return node_base<Off>(m) + (fluid ? q : kOpp[q]) * kTile;
 }
 
 // ------------------------------------------------------------- step kernels --
 // S is the storage type: double (FP64 arithmetic in the oracle's order),
 // float or _Float16 (deviation storage, FP32 arithmetic). TRT selects the
 // collision (BGK or TRT) at compile time, so each kernel only holds the
-// registers of its own operator.
+// registers of its own operator. Off is the slot type (above).
 
-template <class S, bool TRT>
+template <class S, bool TRT, class Off>
 __global__ void __launch_bounds__(kBlock)
 aa_even(S* __restrict__ F, int32_t N, Collision c, int chunk) {
   const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  S* Fn = F + node_base(n);
+  S* Fn = F + node_base<Off>(n);
   S f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = __builtin_nontemporal_load(Fn + q * kTile);
@@ -183,7 +190,7 @@ aa_even(S* __restrict__ F, int32_t N, Collision c, int chunk) {
 // nothing, and FP64 would spill.
 template <class S> struct OddWaves { static constexpr int value = sizeof(S) == 2 ? 6 : 1; };
 
-template <class S, class Idx, bool TRT>
+template <class S, class Idx, bool TRT, class Off>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OddWaves<S>::value)))
 aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int chunk) {
   const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
@@ -191,9 +198,9 @@ aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int chunk) {
   const int32_t n = (int32_t)n64;
   int32_t a[18];
   idx.get(n, a);
-  int32_t slot[Q];
+  Off slot[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) slot[q] = aa_slot(q, n, a);
+  for (int q = 0; q < Q; ++q) slot[q] = aa_slot<Off>(q, n, a);
   S f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = F[slot[q]];
@@ -203,7 +210,7 @@ aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int chunk) {
   for (int q = 0; q < Q; ++q) F[slot[kOpp[q]]] = f[q];
 }
 
-template <class S, class Idx, bool TRT>
+template <class S, class Idx, bool TRT, class Off>
 __global__ void __launch_bounds__(kBlock)
 osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, Idx idx, Collision c, int chunk) {
   const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
@@ -211,14 +218,14 @@ osnt(const S* __restrict__ G, S* __restrict__ H, int32_t N, Idx idx, Collision c
   const int32_t n = (int32_t)n64;
   int32_t a[18];
   idx.get(n, a);
-  int32_t slot[Q];
+  Off slot[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) slot[q] = pull_slot(q, n, a);
+  for (int q = 0; q < Q; ++q) slot[q] = pull_slot<Off>(q, n, a);
   S f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = G[slot[q]];
   Prec<S>::template collide<TRT>(f, c);
-  S* Hn = H + node_base(n);
+  S* Hn = H + node_base<Off>(n);
 #pragma unroll
   for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(f[q], Hn + q * kTile);
 }

@@ -38,24 +38,25 @@ namespace {
 constexpr int kRedBlocks = 1024;  // fixed grid of the reduction: deterministic sums
 
 // Which slots hold f(t) for node n: natural (AA at even t), L (AA at odd t)
-// or the pull map P (OS-NT).
+// or the pull map P (OS-NT). The kernels outside the time loop take 64-bit
+// slots for every lattice.
 enum Layout : int { kNatural = 0, kAAOdd = 1, kPull = 2 };
 
 template <class Idx>
-__device__ __forceinline__ void state_slots(int layout, int32_t n, const Idx& idx, int32_t (&s)[Q]) {
+__device__ __forceinline__ void state_slots(int layout, int32_t n, const Idx& idx, int64_t (&s)[Q]) {
   if (layout == kNatural) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] = pdf_slot(q, n);
+    for (int q = 0; q < Q; ++q) s[q] = pdf_slot<int64_t>(q, n);
     return;
   }
   int32_t a[18];
   idx.get(n, a);
   if (layout == kAAOdd) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] = aa_slot(q, n, a);
+    for (int q = 0; q < Q; ++q) s[q] = aa_slot<int64_t>(q, n, a);
   } else {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] = pull_slot(q, n, a);
+    for (int q = 0; q < Q; ++q) s[q] = pull_slot<int64_t>(q, n, a);
   }
 }
 
@@ -75,7 +76,7 @@ init_eq(S* __restrict__ F, int32_t N, Idx idx, int layout,
   } else {
     equilibrium_f64(r, ux, uy, uz, v);
   }
-  int32_t s[Q];
+  int64_t s[Q];
   state_slots(layout, n, idx, s);
 #pragma unroll
   for (int q = 0; q < Q; ++q) F[s[q]] = Prec<S>::from64(q, v[q], c);
@@ -89,7 +90,7 @@ gather_pdfs(const S* __restrict__ F, int32_t N, Idx idx, int layout, Collision c
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  int32_t s[Q];
+  int64_t s[Q];
   state_slots(layout, n, idx, s);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -105,7 +106,7 @@ scatter_pdfs(S* __restrict__ F, int32_t N, Idx idx, int layout, Collision c,
   const int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
-  int32_t s[Q];
+  int64_t s[Q];
   state_slots(layout, n, idx, s);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -126,7 +127,7 @@ moments(const S* __restrict__ F, int32_t N, Idx idx, int layout, Collision c,
   for (int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x; n64 < N;
        n64 += (int64_t)gridDim.x * kBlock) {
     const int32_t n = (int32_t)n64;
-    int32_t s[Q];
+    int64_t s[Q];
     state_slots(layout, n, idx, s);
     double f[Q];
 #pragma unroll
@@ -167,7 +168,7 @@ weighted_momentum(const S* __restrict__ F, int32_t N, Idx idx, int layout, Colli
   for (int64_t n64 = (int64_t)blockIdx.x * kBlock + threadIdx.x; n64 < N;
        n64 += (int64_t)gridDim.x * kBlock) {
     const int32_t n = (int32_t)n64;
-    int32_t s[Q];
+    int64_t s[Q];
     state_slots(layout, n, idx, s);
     double f[Q];
 #pragma unroll
@@ -286,9 +287,9 @@ int device_status(const char* what) {
   return LBM_OK;
 }
 
-IndexIA index_ia(const lbm_solver* s) { return IndexIA{s->b.adj, (int32_t)s->p.lda}; }
+IndexIA index_ia(const lbm_solver* s) { return IndexIA{s->b.adj, s->p.lda}; }
 IndexRIA index_ria(const lbm_solver* s) {
-  return IndexRIA{s->b.run_delta, s->b.head_bits, s->b.run_base, (int32_t)s->p.ldr};
+  return IndexRIA{s->b.run_delta, s->b.head_bits, s->b.run_base, s->p.ldr};
 }
 IndexRIADir index_ria_dir(const lbm_solver* s) {
   return IndexRIADir{s->b.run_delta, s->b.head_bits, s->b.run_base};
@@ -302,6 +303,16 @@ void with_index(const lbm_solver* s, Go&& go) {
     case LBM_INDEX_DIRECTION_RUNS: go(index_ria_dir(s)); break;
     default: go(index_ia(s)); break;
   }
+}
+
+// Call go(Off{}) with the slot type of the time-step kernels: 32-bit while
+// the grid's 19 * ldf elements fit in 31 bits, 64-bit for larger grids.
+template <class Go>
+void with_slots(const lbm_solver* s, Go&& go) {
+  if ((int64_t)Q * s->p.ldf > (int64_t)INT32_MAX)
+    go(int64_t{});
+  else
+    go(int32_t{});
 }
 
 // Layout of f(t) in the current grid.
@@ -384,7 +395,7 @@ inline unsigned chunked_grid(unsigned tiles, int chunk) {
   return chunk > 0 ? (tiles + m - 1) / m * m : tiles;
 }
 
-template <bool TRT>
+template <bool TRT, class Off>
 void launch_step_op(lbm_solver* s, int32_t N) {
   const unsigned tiles = grid_for(N);
   const dim3 b(kBlock);
@@ -394,8 +405,8 @@ void launch_step_op(lbm_solver* s, int32_t N) {
       dispatch(s, s->b.pdf[0], [&](auto* F, auto) {
         using S = std::remove_pointer_t<decltype(F)>;
         const int chunk = s->remap ? kEvenChunk : 0;
-        hipLaunchKernelGGL((aa_even<S, TRT>), dim3(chunked_grid(tiles, chunk)), b, s->even_lds, s->stream, F,
-                           N, s->c, chunk);
+        hipLaunchKernelGGL((aa_even<S, TRT, Off>), dim3(chunked_grid(tiles, chunk)), b, s->even_lds, s->stream,
+                           F, N, s->c, chunk);
       });
     } else {
       // the scattered stores of the odd step share partial lines between
@@ -403,8 +414,8 @@ void launch_step_op(lbm_solver* s, int32_t N) {
       const int chunk = s->remap ? kOddChunk : 0;
       dispatch(s, s->b.pdf[0], [&](auto* F, auto idx) {
         using S = std::remove_pointer_t<decltype(F)>;
-        hipLaunchKernelGGL((aa_odd<S, decltype(idx), TRT>), dim3(chunked_grid(tiles, chunk)), b, 0, s->stream,
-                           F, N, idx, s->c, chunk);
+        hipLaunchKernelGGL((aa_odd<S, decltype(idx), TRT, Off>), dim3(chunked_grid(tiles, chunk)), b, 0,
+                           s->stream, F, N, idx, s->c, chunk);
       });
     }
   } else {
@@ -413,7 +424,7 @@ void launch_step_op(lbm_solver* s, int32_t N) {
     const int chunk = s->remap ? kPullChunk : 0;
     dispatch(s, G, [&](auto* Gt, auto idx) {
       using S = std::remove_pointer_t<decltype(Gt)>;
-      hipLaunchKernelGGL((osnt<S, decltype(idx), TRT>), dim3(chunked_grid(tiles, chunk)), b, s->pull_lds,
+      hipLaunchKernelGGL((osnt<S, decltype(idx), TRT, Off>), dim3(chunked_grid(tiles, chunk)), b, s->pull_lds,
                          s->stream, (const S*)Gt, (S*)H, N, idx, s->c, chunk);
     });
   }
@@ -426,11 +437,12 @@ void launch_step_pbb(lbm_solver* s, int32_t N, double* save) {
   // the odd step's tile order (the even step of the PBB path shares it)
   const int chunk = s->remap ? kOddChunk : 0;
   const dim3 grid(chunked_grid(grid_for(N), chunk));
-  auto go = [&](auto idx) {
+  auto go = [&](auto idx, auto off) {
     using I = decltype(idx);
+    using Off = decltype(off);
     auto launch = [&](auto odd, auto keep) {
-      hipLaunchKernelGGL((aa_step_pbb<I, decltype(odd)::value, decltype(keep)::value>), grid, dim3(kBlock), 0,
-                         s->stream, F, N, idx, s->c, s->b.solid_frac, save, chunk);
+      hipLaunchKernelGGL((aa_step_pbb<I, decltype(odd)::value, decltype(keep)::value, Off>), grid, dim3(kBlock),
+                         0, s->stream, F, N, idx, s->c, s->b.solid_frac, save, chunk);
     };
     const bool odd = s->t % 2 != 0;
     if (save)
@@ -438,7 +450,7 @@ void launch_step_pbb(lbm_solver* s, int32_t N, double* save) {
     else
       odd ? launch(std::true_type{}, std::false_type{}) : launch(std::false_type{}, std::false_type{});
   };
-  with_index(s, go);
+  with_index(s, [&](auto idx) { with_slots(s, [&](auto off) { go(idx, off); }); });
 }
 
 int launch_step(lbm_solver* s) {
@@ -446,15 +458,22 @@ int launch_step(lbm_solver* s) {
   if (N > 0 && s->b.solid_frac) {
     launch_step_pbb(s, N, nullptr);
   } else if (N > 0) {
-    if (s->trt)
-      launch_step_op<true>(s, N);
-    else
-      launch_step_op<false>(s, N);
+    with_slots(s, [&](auto off) {
+      using Off = decltype(off);
+      if (s->trt)
+        launch_step_op<true, Off>(s, N);
+      else
+        launch_step_op<false, Off>(s, N);
+    });
   }
   if (s->p.pattern == LBM_PATTERN_OSNT) s->cur = 1 - s->cur;
   s->t += 1;
   return LBM_OK;
 }
+
+// Node and run indices are 32-bit, so no leading dimension needs more than
+// 2^31 entries (N <= 2^31 - 65 rounds up to at most 2^31 - 64).
+constexpr int64_t kMaxLd = (int64_t)1 << 31;
 
 int validate(const lbm_params* p, const lbm_buffers* b) {
   if (!p || !b) return fail(LBM_EINVAL, "null params or buffers");
@@ -476,7 +495,7 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
   if (p->n_fluid < 0) return fail(LBM_EINVAL, "n_fluid < 0");
   if (p->n_fluid > INT32_MAX - 64) return fail(LBM_ERANGE, "n_fluid exceeds the int32 node index");
   if (p->ldf < p->n_fluid || p->ldf % 64 != 0) return fail(LBM_EINVAL, "ldf must be >= N and a multiple of 64");
-  if (p->ldf > (int64_t)INT32_MAX / Q) return fail(LBM_ERANGE, "19 * ldf exceeds the int32 slot index");
+  if (p->ldf > kMaxLd) return fail(LBM_ERANGE, "ldf exceeds 2^31");
   if (!b->pdf[0]) return fail(LBM_EINVAL, "pdf[0] is null");
   if (p->pattern == LBM_PATTERN_OSNT && !b->pdf[1]) return fail(LBM_EINVAL, "OS-NT needs pdf[1]");
   if (b->solid_frac && (p->pattern != LBM_PATTERN_AA || p->precision != LBM_F64 || p->collision != LBM_BGK))
@@ -489,12 +508,12 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
   } else if (p->ria == LBM_INDEX_RUNS) {
     if (p->n_runs < 0 || (p->n_fluid > 0 && p->n_runs < 1)) return fail(LBM_EINVAL, "n_runs invalid");
     if (p->ldr < p->n_runs) return fail(LBM_EINVAL, "ldr < n_runs");
-    if (p->ldr > (int64_t)INT32_MAX / 18) return fail(LBM_ERANGE, "18 * ldr exceeds int32");
+    if (p->ldr > kMaxLd) return fail(LBM_ERANGE, "ldr exceeds 2^31");
     if (p->n_fluid > 0 && (!b->run_delta || !b->head_bits || !b->run_base))
       return fail(LBM_EINVAL, "RIA needs run_delta, head_bits and run_base");
   } else {
     if (p->lda < p->n_fluid) return fail(LBM_EINVAL, "lda < n_fluid");
-    if (p->lda > (int64_t)INT32_MAX / 18) return fail(LBM_ERANGE, "18 * lda exceeds int32");
+    if (p->lda > kMaxLd) return fail(LBM_ERANGE, "lda exceeds 2^31");
     if (p->n_fluid > 0 && !b->adj) return fail(LBM_EINVAL, "adjacency list is null");
   }
   return LBM_OK;
@@ -520,7 +539,7 @@ int lbm_required_bytes(const lbm_params* p, int64_t* pdf_bytes_per_grid, int64_t
   if (p->n_fluid > INT32_MAX - 64) return fail(LBM_ERANGE, "n_fluid exceeds the int32 node index");
   const int64_t ldf = p->ldf == 0 ? (std::max<int64_t>(p->n_fluid, 1) + 63) / 64 * 64 : p->ldf;
   if (ldf < p->n_fluid || ldf % 64 != 0) return fail(LBM_EINVAL, "ldf must be 0, or >= N and a multiple of 64");
-  if (ldf > (int64_t)INT32_MAX / Q) return fail(LBM_ERANGE, "19 * ldf exceeds the int32 slot index");
+  if (ldf > kMaxLd) return fail(LBM_ERANGE, "ldf exceeds 2^31");
   const int64_t elem = p->precision == LBM_F64 ? 8 : (p->precision == LBM_F32 ? 4 : 2);
   *pdf_bytes_per_grid = Q * ldf * elem;
   return lbm_solver_workspace_bytes(p, workspace_bytes);
@@ -816,16 +835,17 @@ int lbm_adjoint_step(lbm_solver* s, const double* fwd, int64_t t, double* lam, d
   if (N == 0) return LBM_OK;
   const int chunk = s->remap ? kOddChunk : 0;
   const dim3 grid(chunked_grid(grid_for(N), chunk));
-  auto go = [&](auto idx) {
+  auto go = [&](auto idx, auto off) {
     using I = decltype(idx);
+    using Off = decltype(off);
     if (t % 2 == 0)
-      hipLaunchKernelGGL((aa_adjoint<I, false>), grid, dim3(kBlock), 0, s->stream, fwd, lam, N, idx, s->c,
+      hipLaunchKernelGGL((aa_adjoint<I, false, Off>), grid, dim3(kBlock), 0, s->stream, fwd, lam, N, idx, s->c,
                          s->b.solid_frac, grad, chunk);
     else
-      hipLaunchKernelGGL((aa_adjoint<I, true>), grid, dim3(kBlock), 0, s->stream, fwd, lam, N, idx, s->c,
+      hipLaunchKernelGGL((aa_adjoint<I, true, Off>), grid, dim3(kBlock), 0, s->stream, fwd, lam, N, idx, s->c,
                          s->b.solid_frac, grad, chunk);
   };
-  with_index(s, go);
+  with_index(s, [&](auto idx) { with_slots(s, [&](auto off) { go(idx, off); }); });
   return device_status("adjoint_step");
 }
 

@@ -54,6 +54,10 @@ def test_valid_parameters_create():
     assert create(params(ria=1), buffers()) == 0
     assert create(params(ria=2, n_runs=18 * 3), buffers()) == 0
     assert create(params(pattern=1, precision=2, collision=1, trt_magic=0.1875), buffers()) == 0
+    # grids beyond 2^31 - 1 elements (64-bit slot offsets) and the largest node count
+    assert create(params(n_fluid=150_000_000, ldf=150_000_000, lda=150_000_000), buffers()) == 0
+    big = 2 ** 31 - 65
+    assert create(params(n_fluid=big, ldf=2 ** 31 - 64, lda=2 ** 31 - 64, pattern=1), buffers()) == 0
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -74,7 +78,10 @@ def test_valid_parameters_create():
     (dict(ldf=64), capi.LBM_EINVAL),             # < N
     (dict(lda=50), capi.LBM_EINVAL),
     (dict(n_fluid=2 ** 31), capi.LBM_ERANGE),
-    (dict(n_fluid=120_000_000, ldf=120_000_000, lda=120_000_000), capi.LBM_ERANGE),  # 19 * ldf > 2^31 - 1
+    (dict(n_fluid=2 ** 31 - 64, ldf=2 ** 31, lda=2 ** 31), capi.LBM_ERANGE),  # node index beyond int32
+    (dict(ldf=2 ** 31 + 64), capi.LBM_ERANGE),
+    (dict(lda=2 ** 31 + 64), capi.LBM_ERANGE),
+    (dict(ria=1, ldr=2 ** 31 + 64), capi.LBM_ERANGE),
     (dict(ria=1, ldr=5), capi.LBM_EINVAL),
     (dict(ria=1, n_runs=0), capi.LBM_EINVAL),
 ])
@@ -162,9 +169,13 @@ def test_required_bytes_per_grid(prec, size):
     assert required(params(precision=prec, n_fluid=100, ldf=0)) == (0, 19 * 128 * size, need.value)
     assert required(params(precision=prec, n_fluid=128, ldf=0))[1] == 19 * 128 * size
     assert required(params(precision=prec, n_fluid=0, ldf=0))[1] == 19 * 64 * size
-    # the largest stride the 32-bit slot offsets allow
+    # the largest stride the 32-bit slot offsets allow, the next one (64-bit
+    # offsets), and the largest node count
     top = (2 ** 31 - 1) // 19 // 64 * 64
     assert required(params(precision=prec, n_fluid=top, ldf=top))[1] == 19 * top * size
+    assert required(params(precision=prec, n_fluid=top + 1, ldf=0))[1] == 19 * (top + 64) * size
+    big = 2 ** 31 - 65
+    assert required(params(precision=prec, n_fluid=big, ldf=0)) == (0, 19 * (2 ** 31 - 64) * size, need.value)
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -173,7 +184,8 @@ def test_required_bytes_per_grid(prec, size):
     (dict(n_fluid=100, ldf=96), capi.LBM_EINVAL),
     (dict(n_fluid=100, ldf=130), capi.LBM_EINVAL),
     (dict(n_fluid=2 ** 31, ldf=0), capi.LBM_ERANGE),
-    (dict(n_fluid=100, ldf=(2 ** 31 - 1) // 19 // 64 * 64 + 64), capi.LBM_ERANGE),
+    (dict(n_fluid=2 ** 31 - 64, ldf=0), capi.LBM_ERANGE),
+    (dict(n_fluid=100, ldf=2 ** 31 + 64), capi.LBM_ERANGE),
 ])
 def test_required_bytes_rejects(kw, code):
     assert required(params(**kw))[0] == code

@@ -2,8 +2,8 @@
 times: sampled sites against the oracle's dependency-cone evaluation after a
 few steps, properties that hold at any size (bitwise identity of all
 propagation variants, mass conservation over many steps), deviation storage
-against the FP64 path, and the largest lattice the 32-bit slot offsets
-allow."""
+against the FP64 path, the largest lattice the 32-bit slot offsets allow,
+and the 512^3 foam, whose grids need 64-bit offsets."""
 import numpy as np
 import pytest
 
@@ -310,3 +310,71 @@ def test_spherepack_trt_sampled_sites(pack, pattern):
     node_of[lat.node_voxel().astype(np.int64)] = np.arange(lat.n_fluid)
     vox = (sites[:, 0] * mask.shape[1] + sites[:, 1]) * mask.shape[2] + sites[:, 2]
     assert np.array_equal(f[:, node_of[vox]].T, want)
+
+
+@pytest.fixture(scope="module")
+def foam512():
+    # the foam recipe at 512^3: N = 114,085,068 nodes, so a grid holds more
+    # than 2^31 - 1 elements and the step kernels take 64-bit slot offsets
+    print("case 64-bit slots: generating the 512^3 foam", flush=True)
+    mask, p = workload("foam-512", seed=0)
+    from paper_1410_0412_amd import Lattice
+    lat = Lattice(mask, p["periodic"], p["order"], p["block"])
+    N = lat.n_fluid
+    top = (2 ** 31 - 1) // 19  # nodes from about here on own slots beyond 2^31 - 1
+    assert 19 * ((N + 63) // 64 * 64) > 2 ** 31 - 1 and N > top
+    steps = 3
+    rho0, u0 = init_fields(mask.shape, seed=61)
+    r, v = node_fields(lat, rho0, u0)
+    nv = lat.node_voxel().astype(np.int64)  # increasing in lexicographic order
+    rng = np.random.default_rng(62)
+    shape = np.array(mask.shape)
+
+    def fluid_sites(lo, hi, count):
+        pts = np.stack([rng.integers(lo[a], hi[a], 4 * count) for a in range(3)], 1)
+        pts = pts[mask[pts[:, 0], pts[:, 1], pts[:, 2]] == 0]
+        return pts[:count]
+
+    # anywhere; the last planes (nodes whose own slots lie beyond 2^31 - 1);
+    # the first plane (periodic neighbours of the last); the last node
+    last = np.array(np.unravel_index(nv[-1], mask.shape))
+    sites = np.concatenate([fluid_sites([0, 0, 0], shape, 24),
+                            fluid_sites([507, 0, 0], shape, 24),
+                            fluid_sites([0, 0, 0], [1, 512, 512], 8), last[None]])
+    vox = (sites[:, 0] * shape[1] + sites[:, 1]) * shape[2] + sites[:, 2]
+    node = np.searchsorted(nv, vox)
+    assert np.array_equal(nv[node], vox)
+    assert (node >= top).sum() >= 20 and node.max() == N - 1
+    want = dense.cone_sites(mask.astype(bool), p["periodic"], p["tau"], p["force"], steps, rho0, u0, sites)
+    del rho0, u0, nv
+    return lat, p, steps, r, v, node, want
+
+
+W_Q = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+@pytest.mark.parametrize("pattern,ria,prec,pbb", [
+    ("aa", "auto", "f64", False), ("osnt", "auto", "f64", False), ("aa", False, "f64", False),
+    ("aa", True, "f64", False), ("osnt", True, "f64", False), ("aa", "auto", "f64", True),
+    ("aa", "auto", "f32", False), ("osnt", "auto", "f32", False), ("aa", "auto", "f16", False)])
+def test_foam512_wide_slots_sampled_sites(foam512, pattern, ria, prec, pbb):
+    # sampled sites after 3 steps against the oracle's dependency cone:
+    # bitwise in FP64 (with partial bounce-back at ns = 0 too), within the
+    # rounding of the storage format in FP32 and FP16 (max |df_q| / w_q;
+    # a value from a wrong slot is off by about 3 |c_q . du| ~ 4e-2)
+    from paper_1410_0412_amd import Solver
+    lat, p, steps, r, v, node, want = foam512
+    s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=prec, pbb=pbb)
+    print("case 64-bit slots:", pattern, "index", s.index, prec, "pbb" if pbb else "", flush=True)
+    s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
+    s.step(steps)
+    f = s.export_pdfs()
+    got = f[:, torch.from_numpy(node).cuda()].T.cpu().numpy()
+    del s, f
+    torch.cuda.empty_cache()
+    if prec == "f64":
+        assert np.array_equal(got, want)
+    else:
+        err = float(np.max(np.abs(got - want) / W_Q))
+        print("max |df_q| / w_q = %.3e" % err, flush=True)
+        assert err <= {"f32": 1e-6, "f16": 5e-4}[prec]
