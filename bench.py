@@ -120,7 +120,10 @@ def measured_traffic(kernel, workload):
 
 
 def kernel_key(name):
-    """Short kernel name of a demangled rocprofv3 kernel name."""
+    """Short kernel name of a demangled rocprofv3 kernel name. The time-step
+    kernels take the slot type (int: 32-bit element offsets, long: 64-bit)
+    as their last template argument; the short name leaves it out, since the
+    lattice size fixes it (``slot_bits``)."""
     name = name.replace("(anonymous namespace)::", "").replace("lbm::", "").replace("void ", "")
     depth, out = 0, []
     for ch in name:
@@ -129,7 +132,18 @@ def kernel_key(name):
         depth += ch == "<"
         depth -= ch == ">"
         out.append(ch)
-    return "".join(out).strip()
+    key = "".join(out).strip()
+    for slot in (", int>", ", long>"):
+        if key.endswith(slot):
+            return key[: -len(slot)] + ">"
+    return key
+
+
+def slot_bits(n_fluid):
+    """Width of the time-step kernels' slot offsets for a lattice of n_fluid
+    nodes: 32 while a grid (19 * ldf elements) fits in 2^31 - 1, else 64."""
+    ldf = (max(int(n_fluid), 1) + 63) // 64 * 64
+    return 32 if 19 * ldf <= 2 ** 31 - 1 else 64
 
 
 def _counter_clusters(path, counters):
@@ -982,6 +996,7 @@ def main_line(torch, args):
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(odd_bytes),
+            "slot_bits": slot_bits(N),
             "avg_launch_us": round(odd_s * 1e6, 2),
             "launch_samples": int(len(main_tm.second)),
             # the counter-measured bytes (traffic) per launch over the same duration

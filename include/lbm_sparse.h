@@ -60,10 +60,13 @@ enum { LBM_BGK = 0, LBM_TRT = 1 };
 /* Neighbour index source of a solver (lbm_params.ria): the adjacency list,
  * the paper's runs (Sect. 4.1) or per-direction runs. */
 enum { LBM_INDEX_ADJ = 0, LBM_INDEX_RUNS = 1, LBM_INDEX_DIRECTION_RUNS = 2 };
-/* Solver flag: launch the step kernels in plain tile order. By default each
- * XCD takes chunks of consecutive 256-node tiles in turn, so neighbouring
- * tiles share an L2. */
-enum { LBM_FLAG_NO_XCD_REMAP = 1 };
+/* Solver flags. LBM_FLAG_NO_XCD_REMAP: launch the step kernels in plain tile
+ * order. By default each XCD takes chunks of consecutive 256-node tiles in
+ * turn, so neighbouring tiles share an L2. LBM_FLAG_WIDE_SLOTS: step with
+ * 64-bit slot offsets whatever the grid size; without it they are 64-bit
+ * only for grids of more than 2^31 - 1 elements. Both forms compute the same
+ * result bit for bit; the flag exercises the wide form on small lattices. */
+enum { LBM_FLAG_NO_XCD_REMAP = 1, LBM_FLAG_WIDE_SLOTS = 2 };
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* lbm_last_error(void);
@@ -180,7 +183,7 @@ typedef struct lbm_params {
                         stores d_q * 2^f16_scale_log2 / w_q in FP16. Both
                         deviation formats collide in FP32; moments, totals and
                         export/import are FP64.                              */
-  int32_t flags;     /* LBM_FLAG_NO_XCD_REMAP, or 0                          */
+  int32_t flags;     /* LBM_FLAG_NO_XCD_REMAP | LBM_FLAG_WIDE_SLOTS, or 0   */
   int64_t n_fluid;   /* N                                                    */
   int64_t n_runs;    /* R (LBM_INDEX_RUNS) or RD (LBM_INDEX_DIRECTION_RUNS) */
   int64_t ldf;       /* node slots of the grid: >= N, a multiple of 64,

@@ -17,6 +17,7 @@ ORDERS = {"lex": 0, "morton": 1, "hilbert": 2, "hilbert_ls": 3}
 PATTERNS = {"aa": 0, "osnt": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2}
 FLAG_NO_XCD_REMAP = 1
+FLAG_WIDE_SLOTS = 2
 INDEX = {"adjacency": 0, "runs": 1, "direction": 2}
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)

@@ -306,10 +306,11 @@ void with_index(const lbm_solver* s, Go&& go) {
 }
 
 // Call go(Off{}) with the slot type of the time-step kernels: 32-bit while
-// the grid's 19 * ldf elements fit in 31 bits, 64-bit for larger grids.
+// the grid's 19 * ldf elements fit in 31 bits, 64-bit for larger grids or
+// when the caller asks for them.
 template <class Go>
 void with_slots(const lbm_solver* s, Go&& go) {
-  if ((int64_t)Q * s->p.ldf > (int64_t)INT32_MAX)
+  if ((s->p.flags & LBM_FLAG_WIDE_SLOTS) || (int64_t)Q * s->p.ldf > (int64_t)INT32_MAX)
     go(int64_t{});
   else
     go(int32_t{});
@@ -487,7 +488,8 @@ int validate(const lbm_params* p, const lbm_buffers* b) {
     return fail(LBM_EINVAL, "ria must be 0, 1 or 2");
   if (p->precision != LBM_F64 && p->precision != LBM_F32 && p->precision != LBM_F16)
     return fail(LBM_EINVAL, "unknown precision %d", p->precision);
-  if (p->flags & ~LBM_FLAG_NO_XCD_REMAP) return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~(LBM_FLAG_NO_XCD_REMAP | LBM_FLAG_WIDE_SLOTS))
+    return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
   if (p->f16_scale_log2 < -24 || p->f16_scale_log2 > 24) return fail(LBM_EINVAL, "f16_scale_log2 out of [-24, 24]");
   if (p->collision != LBM_BGK && p->collision != LBM_TRT) return fail(LBM_EINVAL, "unknown collision %d", p->collision);
   if (p->collision == LBM_TRT && !(p->trt_magic > 0 && std::isfinite(p->trt_magic)))

@@ -108,11 +108,14 @@ class Solver:
                (``solid_frac``, zero-initialised; AA, FP64, BGK only).
     xcd_remap  step kernels: each XCD takes chunks of consecutive tiles in
                turn (False: plain tile order).
+    wide_slots step kernels: 64-bit slot offsets even where 32-bit ones
+               suffice (grids of at most 2^31 - 1 elements); the same
+               result bit for bit.
     """
 
     def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria="auto",
                  precision="f64", rho0=1.0, device=None, xcd_remap=True, f16_scale_log2=10,
-                 trt_magic=None, pbb=False):
+                 trt_magic=None, pbb=False, wide_slots=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -165,7 +168,7 @@ class Solver:
             p.pattern = _capi.PATTERNS[pattern]
             p.ria = _capi.INDEX[self.index]
             p.precision = _capi.PRECISIONS[precision]
-            p.flags = 0 if xcd_remap else _capi.FLAG_NO_XCD_REMAP
+            p.flags = (0 if xcd_remap else _capi.FLAG_NO_XCD_REMAP) | (_capi.FLAG_WIDE_SLOTS if wide_slots else 0)
             p.n_fluid, p.n_runs, p.ldf, p.lda, p.ldr = N, R, self.ldf, lda, ldr
             p.f16_scale_log2 = int(f16_scale_log2)
             p.collision = 0 if trt_magic is None else 1

@@ -51,6 +51,12 @@ def test_source_digest_covers_the_device_sources():
 def test_kernel_key():
     assert bench.kernel_key("void lbm::aa_odd<double, lbm::IndexRIADir, false>(double*, int, lbm::IndexRIADir, "
                             "lbm::Collision, int)") == "aa_odd<double, IndexRIADir, false>"
+    # the slot-type argument of the time-step kernels is left out
+    for slot in ("int", "long"):
+        assert bench.kernel_key("void lbm::aa_odd<double, lbm::IndexRIADir, false, %s>(double*, int, "
+                                "lbm::IndexRIADir, lbm::Collision, int)" % slot) == "aa_odd<double, IndexRIADir, false>"
+        assert bench.kernel_key("void lbm::aa_even<float, true, %s>(float*, int, lbm::Collision, int)"
+                                % slot) == "aa_even<float, true>"
     assert bench.kernel_key("(anonymous namespace)::bench_copy(double const*, double*, long)") == "bench_copy"
 
 
@@ -184,3 +190,10 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
+
+
+def test_slot_bits_threshold():
+    # 32-bit slot offsets while 19 * ldf <= 2^31 - 1 (ldf = N rounded up to 64)
+    top = (2 ** 31 - 1) // 19 // 64 * 64
+    assert bench.slot_bits(top) == 32 and bench.slot_bits(top + 1) == 64
+    assert bench.slot_bits(48_129_638) == 32 and bench.slot_bits(114_085_068) == 64

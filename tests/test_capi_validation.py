@@ -54,6 +54,8 @@ def test_valid_parameters_create():
     assert create(params(ria=1), buffers()) == 0
     assert create(params(ria=2, n_runs=18 * 3), buffers()) == 0
     assert create(params(pattern=1, precision=2, collision=1, trt_magic=0.1875), buffers()) == 0
+    # both flags; 64-bit slots asked for on a small grid
+    assert create(params(flags=capi.FLAG_NO_XCD_REMAP | capi.FLAG_WIDE_SLOTS), buffers()) == 0
     # grids beyond 2^31 - 1 elements (64-bit slot offsets) and the largest node count
     assert create(params(n_fluid=150_000_000, ldf=150_000_000, lda=150_000_000), buffers()) == 0
     big = 2 ** 31 - 65
@@ -70,7 +72,7 @@ def test_valid_parameters_create():
     (dict(ria=2, n_runs=17), capi.LBM_EINVAL),   # every direction has at least one run
     (dict(ria=2, n_runs=2 ** 31), capi.LBM_ERANGE),
     (dict(precision=3), capi.LBM_EINVAL),
-    (dict(flags=2), capi.LBM_EINVAL),
+    (dict(flags=4), capi.LBM_EINVAL),
     (dict(collision=1, trt_magic=0.0), capi.LBM_EINVAL),
     (dict(collision=2), capi.LBM_EINVAL),
     (dict(f16_scale_log2=30), capi.LBM_EINVAL),

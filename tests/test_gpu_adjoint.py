@@ -121,6 +121,24 @@ def test_gradient_matches_autograd(small, ria, every):
     assert err <= 2e-12, err
 
 
+@pytest.mark.parametrize("ria", [False, True, "direction"])
+def test_wide_slots_gradient_bitwise(small, ria):
+    # the partial-bounce-back, state-saving and adjoint step kernels with
+    # 64-bit slot offsets (the form grids of more than 2^31 - 1 elements
+    # take) give the same J and gradient as the 32-bit form, bit for bit
+    from paper_1410_0412_amd import outlet_flux
+    mask, ns, w = small
+    out = []
+    for wide in (False, True):
+        lat, s = solver_for(mask, PER, 0.8, (1e-5, 0, 0), "aa", ria, pbb=True, wide_slots=wide)
+        x = torch.from_numpy(nodes_of(lat, ns)).cuda().requires_grad_(True)
+        J = outlet_flux(x, s, 12, 5, torch.from_numpy(nodes_of(lat, w)).cuda())
+        J.backward()
+        out.append((J.item(), x.grad.cpu().numpy()))
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_checkpoint_interval_does_not_change_gradient(small):
     from paper_1410_0412_amd import outlet_flux
     mask, ns, w = small

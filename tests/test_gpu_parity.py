@@ -67,6 +67,34 @@ def test_every_step_random_state(pattern, ria, order, block):
 
 
 @pytest.mark.parametrize("pattern,ria", VARIANTS)
+@pytest.mark.parametrize("prec,trt", [("f64", None), ("f64", 0.1875), ("f32", None), ("f32", 0.1875), ("f16", None)])
+def test_wide_slots_every_step(pattern, ria, prec, trt):
+    # the step kernels with 64-bit slot offsets (the form grids of more than
+    # 2^31 - 1 elements take) against the 32-bit form after every step, bit
+    # for bit, in every precision and with both collisions; FP64 against the
+    # oracle too
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.25, PER, seed=5)
+    rho0, u0 = init_fields(mask.shape, seed=6)
+    tau, F = 0.65, (2e-5, -1e-5, 5e-6)
+    print("case wide slots", pattern, ria, prec, trt, flush=True)
+    lat, a = solver_for(mask, PER, tau, F, pattern, ria, precision=prec, trt_magic=trt, wide_slots=True)
+    _, b = solver_for(mask, PER, tau, F, pattern, ria, precision=prec, trt_magic=trt)
+    r, v = node_fields(lat, rho0, u0)
+    r, v = torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda()
+    a.init(r, v)
+    b.init(r, v)
+    f = dense.initial_state(mask.astype(bool), rho0, u0)
+    for t in range(1, 8):
+        a.step(1)
+        b.step(1)
+        fa = a.export_pdfs()
+        assert torch.equal(fa, b.export_pdfs()), t
+        if prec == "f64":
+            f = dense.step(f, mask.astype(bool), PER, tau, F, trt)
+            assert np.array_equal(fa.cpu().numpy(), oracle_at_nodes(lat, f)), t
+
+
+@pytest.mark.parametrize("pattern,ria", VARIANTS)
 def test_import_export_roundtrip(pattern, ria):
     mask = rsa_spheres((16, 16, 16), 2.0, 0.2, PER, seed=7)
     rho0, u0 = init_fields(mask.shape, seed=8)
