@@ -127,10 +127,11 @@ struct IndexRIADir {
 
 // Slots are element offsets into the grid, of type Off: int32_t while the
 // grid holds at most 2^31 - 1 elements (19 * ldf, lattices of up to
-// 113 M nodes), int64_t beyond. The 32-bit form keeps the 19 slots the odd
-// step holds across the collision in 19 registers; 64-bit slots take two
-// each. Node indices stay 32-bit (N < 2^31). Per lane a slot costs a
-// compare, two selects and a few integer operations, with no branch.
+// 113 M nodes), int64_t beyond, so that one grid can fill the device. The
+// 32-bit form needs no 64-bit integer arithmetic per slot; the host takes
+// it whenever the grid allows. Node indices stay 32-bit (N < 2^31). Per
+// lane a slot costs a compare, two selects and a few integer operations,
+// with no branch.
 constexpr int32_t kTile = 64;
 
 // Offset of direction 0 of node m; direction q lies q * 64 elements further.
