@@ -119,7 +119,9 @@ int lbm_lattice_sizes(const lbm_lattice* lat, int64_t* n_fluid, int64_t* n_runs,
 int lbm_lattice_copy_nodes(const lbm_lattice* lat, int32_t* node_voxel);
 
 /* adj: host int32[18*ld], ld >= N; entry of direction q (1..18) for node n at
- * adj[(q-1)*ld + n]. Columns N..ld-1 are filled with -1. */
+ * adj[(q-1)*ld + n]. Columns N..ld-1 are filled with -1. The lattice stores
+ * no adjacency list (72 B per node); this call computes it from the
+ * voxel-to-node map the lattice keeps (4 B per voxel). */
 int lbm_lattice_copy_adjacency(const lbm_lattice* lat, int32_t* adj, int64_t ld);
 
 /* run_start: host int32[R+1]; first node of each run, then N (the block

@@ -10,6 +10,10 @@
 //
 // All tables are built in O(voxels) passes that run in parallel over node or
 // voxel ranges; only the Morton order needs a sort (LSD radix on the keys).
+// The adjacency list itself (72 B per node) is never stored: the lattice
+// keeps the voxel-to-node map (4 B per voxel) and computes a node's 18
+// entries when a table or a caller needs them, so a lattice that fills a
+// 288 GB device can be built with a small fraction of that in host memory.
 
 #include "common.hpp"
 
@@ -26,9 +30,10 @@ using namespace lbm;
 
 struct lbm_lattice {
   int32_t nx = 0, ny = 0, nz = 0;
+  uint32_t periodic = 0;            // bit a: axis a periodic
   int64_t N = 0, R = 0, W = 0;
   std::vector<int32_t> node_voxel;  // [N]
-  std::vector<int32_t> adj;         // [18][N]
+  std::vector<int32_t> node_of;     // [nx*ny*nz]: node of a voxel, -1 if solid
   std::vector<int32_t> run_start;   // [R+1]
   std::vector<int32_t> run_delta;   // [18][R]
   std::vector<uint64_t> head_bits;  // [W]
@@ -152,6 +157,11 @@ int enumerate(lbm_lattice* L, const uint8_t* solid, int32_t order, int32_t block
   const int64_t nx = L->nx, ny = L->ny, nz = L->nz;
   auto& out = L->node_voxel;
   const int64_t maxext = std::max(nx, std::max(ny, nz));
+  {
+    int64_t fluid = 0;
+    for (int64_t v = 0; v < nx * ny * nz; ++v) fluid += solid[v] == 0;
+    out.reserve((size_t)fluid);
+  }
   if (order == LBM_ORDER_LEX) {
     const int64_t B = block;
     if (B <= 1 || B >= maxext) {
@@ -208,104 +218,98 @@ int enumerate(lbm_lattice* L, const uint8_t* solid, int32_t order, int32_t block
   return fail(LBM_EINVAL, "unknown order %d", order);
 }
 
-void build_adjacency(lbm_lattice* L, uint32_t periodic) {
-  const int64_t nx = L->nx, ny = L->ny, nz = L->nz, N = L->N;
-  const int64_t ext[3] = {nx, ny, nz};
-  std::vector<int32_t> node_of((size_t)(nx * ny * nz), -1);
-  parallel_for(N, [&](int64_t lo, int64_t hi) {
-    for (int64_t n = lo; n < hi; ++n) node_of[L->node_voxel[n]] = (int32_t)n;
-  });
-  L->adj.assign((size_t)(18 * N), -1);
-  parallel_for(N, [&](int64_t lo, int64_t hi) {
-    for (int64_t n = lo; n < hi; ++n) {
-      const int64_t v = L->node_voxel[n];
-      const int64_t x[3] = {v / (ny * nz), (v / nz) % ny, v % nz};
-      for (int q = 1; q < 19; ++q) {
-        int64_t u[3];
-        bool inside = true;
-        for (int a = 0; a < 3; ++a) {
-          u[a] = x[a] - kC[q][a];
-          if (u[a] < 0 || u[a] >= ext[a]) {
-            if (periodic & (1u << a))
-              u[a] = (u[a] + ext[a]) % ext[a];
-            else
-              inside = false;
-          }
-        }
-        int32_t nb = -1;
-        if (inside) nb = node_of[(u[0] * ny + u[1]) * nz + u[2]];
-        L->adj[(size_t)(q - 1) * N + n] = nb;
-      }
-    }
+void build_node_map(lbm_lattice* L) {
+  const int64_t V = (int64_t)L->nx * L->ny * L->nz;
+  L->node_of.assign((size_t)V, -1);
+  parallel_for(L->N, [&](int64_t lo, int64_t hi) {
+    for (int64_t n = lo; n < hi; ++n) L->node_of[L->node_voxel[n]] = (int32_t)n;
   });
 }
 
-void build_runs(lbm_lattice* L) {
-  const int64_t N = L->N;
-  std::vector<uint8_t> head((size_t)N, 1);
-  const int32_t* A = L->adj.data();
-  parallel_for(N, [&](int64_t lo, int64_t hi) {
-    for (int64_t n = std::max<int64_t>(lo, 1); n < hi; ++n) {
-      bool cont = true;
-      for (int q = 0; q < 18 && cont; ++q) {
-        const int32_t p = A[(size_t)q * N + n - 1], c = A[(size_t)q * N + n];
-        cont = (p >= 0) ? (c == p + 1) : (c < 0);
-      }
-      head[n] = cont ? 0 : 1;
+// Adjacency entry of node n for direction q = 1..18 (pull: the node at
+// x_n - c_q, or -1 if that site is solid or outside a non-periodic axis).
+inline int32_t neighbour(const lbm_lattice* L, int64_t n, int q) {
+  const int64_t ext[3] = {L->nx, L->ny, L->nz};
+  const int64_t v = L->node_voxel[n];
+  const int64_t x[3] = {v / (ext[1] * ext[2]), (v / ext[2]) % ext[1], v % ext[2]};
+  int64_t u[3];
+  for (int a = 0; a < 3; ++a) {
+    u[a] = x[a] - kC[q][a];
+    if (u[a] < 0 || u[a] >= ext[a]) {
+      if (!(L->periodic & (1u << a))) return -1;
+      u[a] = (u[a] + ext[a]) % ext[a];
     }
-  });
-  L->run_start.clear();
-  for (int64_t n = 0; n < N; ++n)
-    if (head[n]) L->run_start.push_back((int32_t)n);
-  L->R = (int64_t)L->run_start.size();
-  L->run_start.push_back((int32_t)N);
-
-  const int64_t R = L->R;
-  L->run_delta.assign((size_t)(18 * R), INT32_MIN);
-  parallel_for(R, [&](int64_t lo, int64_t hi) {
-    for (int64_t r = lo; r < hi; ++r) {
-      const int64_t h = L->run_start[r];
-      for (int q = 0; q < 18; ++q) {
-        const int32_t a = A[(size_t)q * N + h];
-        L->run_delta[(size_t)q * R + r] = a >= 0 ? (int32_t)(a - h) : INT32_MIN;
-      }
-    }
-  });
-
-  const int64_t W = (N + kWave - 1) / kWave;
-  L->W = W;
-  L->head_bits.assign((size_t)W, 0);
-  L->run_base.assign((size_t)W, 0);
-  for (int64_t n = 0; n < N; ++n)
-    if (head[n]) L->head_bits[n / kWave] |= (uint64_t)1 << (n % kWave);
-  int64_t heads_below = 0;
-  for (int64_t w = 0; w < W; ++w) {
-    L->run_base[w] = (int32_t)(heads_below - 1);
-    heads_below += __builtin_popcountll(L->head_bits[w]);
   }
+  return L->node_of[(u[0] * ext[1] + u[1]) * ext[2] + u[2]];
 }
 
-// Per-direction runs: the run rule above applied to one direction at a time.
-// Runs of direction q are numbered after those of directions 1..q-1.
-void build_direction_runs(lbm_lattice* L) {
-  const int64_t N = L->N, W = L->W;
-  const int32_t* A = L->adj.data();
+inline void adjacency_of(const lbm_lattice* L, int64_t n, int32_t (&a)[18]) {
+  for (int q = 1; q < 19; ++q) a[q - 1] = neighbour(L, n, q);
+}
+
+// The run rule of Sect. 4.1 for one direction: node n continues the run of
+// n - 1 when its entry is the previous one shifted by one, or both are solid.
+inline bool continues(int32_t prev, int32_t cur) { return prev >= 0 ? cur == prev + 1 : cur < 0; }
+
+// Per-direction run heads, then the paper's (joint) runs: a node heads a
+// joint run exactly when it heads a run of at least one direction. Runs of
+// direction q are numbered after those of directions 1..q-1.
+void build_runs(lbm_lattice* L) {
+  const int64_t N = L->N, W = (N + kWave - 1) / kWave;
+  L->W = W;
   L->dir_bits.assign((size_t)(W * 18), 0);
-  L->dir_base.assign((size_t)(W * 18), 0);
   parallel_for(W, [&](int64_t lo, int64_t hi) {
+    int32_t a[kWave + 1][18];
     for (int64_t w = lo; w < hi; ++w) {
       const int64_t n0 = w * kWave, n1 = std::min(N, n0 + kWave);
+      // row 0 holds node n0 - 1 (none for the first wave)
+      if (n0 > 0) adjacency_of(L, n0 - 1, a[0]);
+      for (int64_t n = n0; n < n1; ++n) adjacency_of(L, n, a[n - n0 + 1]);
       for (int q = 0; q < 18; ++q) {
-        const int32_t* a = A + (size_t)q * N;
         uint64_t bits = 0;
         for (int64_t n = n0; n < n1; ++n) {
-          const bool cont = n > 0 && ((a[n - 1] >= 0) ? (a[n] == a[n - 1] + 1) : (a[n] < 0));
+          const bool cont = n > 0 && continues(a[n - n0][q], a[n - n0 + 1][q]);
           if (!cont) bits |= (uint64_t)1 << (n - n0);
         }
         L->dir_bits[(size_t)w * 18 + q] = bits;
       }
     }
   });
+
+  // joint runs
+  L->head_bits.assign((size_t)W, 0);
+  L->run_base.assign((size_t)W, 0);
+  for (int64_t w = 0; w < W; ++w) {
+    uint64_t h = 0;
+    for (int q = 0; q < 18; ++q) h |= L->dir_bits[(size_t)w * 18 + q];
+    L->head_bits[w] = h;
+  }
+  L->run_start.clear();
+  int64_t heads_below = 0;
+  for (int64_t w = 0; w < W; ++w) {
+    L->run_base[w] = (int32_t)(heads_below - 1);
+    uint64_t bits = L->head_bits[w];
+    heads_below += __builtin_popcountll(bits);
+    while (bits) {
+      L->run_start.push_back((int32_t)(w * kWave + __builtin_ctzll(bits)));
+      bits &= bits - 1;
+    }
+  }
+  L->R = (int64_t)L->run_start.size();
+  L->run_start.push_back((int32_t)N);
+  const int64_t R = L->R;
+  L->run_delta.assign((size_t)(18 * R), INT32_MIN);
+  parallel_for(R, [&](int64_t lo, int64_t hi) {
+    int32_t a[18];
+    for (int64_t r = lo; r < hi; ++r) {
+      const int64_t h = L->run_start[r];
+      adjacency_of(L, h, a);
+      for (int q = 0; q < 18; ++q) L->run_delta[(size_t)q * R + r] = a[q] >= 0 ? (int32_t)(a[q] - h) : INT32_MIN;
+    }
+  });
+
+  // per-direction run bases and deltas
+  L->dir_base.assign((size_t)(W * 18), 0);
   int64_t first = 0;
   for (int q = 0; q < 18; ++q) {
     int64_t below = 0;
@@ -333,14 +337,14 @@ void build_direction_runs(lbm_lattice* L) {
   parallel_for(W, [&](int64_t lo, int64_t hi) {
     for (int64_t w = lo; w < hi; ++w)
       for (int q = 0; q < 18; ++q) {
-        const int32_t* a = A + (size_t)q * N;
         uint64_t bits = L->dir_bits[(size_t)w * 18 + q];
         int64_t r = (int64_t)L->dir_base[(size_t)w * 18 + q];
         while (bits) {
           const int l = __builtin_ctzll(bits);
           bits &= bits - 1;
           const int64_t h = w * kWave + l;
-          L->dir_delta[(size_t)++r] = a[h] >= 0 ? (int32_t)(a[h] - h) : INT32_MIN;
+          const int32_t a = neighbour(L, h, q + 1);
+          L->dir_delta[(size_t)++r] = a >= 0 ? (int32_t)(a - h) : INT32_MIN;
         }
       }
   });
@@ -375,9 +379,9 @@ int lbm_lattice_build(const uint8_t* solid, int32_t nx, int32_t ny, int32_t nz,
       return rc;
     }
     L->N = (int64_t)L->node_voxel.size();
-    build_adjacency(L, periodic_mask);
+    L->periodic = periodic_mask;
+    build_node_map(L);
     build_runs(L);
-    build_direction_runs(L);
   } catch (const std::bad_alloc&) {
     delete L;
     return fail(LBM_ENOMEM, "out of host memory building the lattice");
@@ -409,10 +413,14 @@ int lbm_lattice_copy_adjacency(const lbm_lattice* L, int32_t* adj, int64_t ld) {
   clear_error();
   if (!L || !adj) return fail(LBM_EINVAL, "null pointer");
   if (ld < L->N) return fail(LBM_EINVAL, "ld < N");
-  for (int q = 0; q < 18; ++q) {
-    if (L->N) std::memcpy(adj + q * ld, L->adj.data() + q * L->N, sizeof(int32_t) * L->N);
-    std::fill(adj + q * ld + L->N, adj + (q + 1) * ld, -1);
-  }
+  parallel_for(L->N, [&](int64_t lo, int64_t hi) {
+    int32_t a[18];
+    for (int64_t n = lo; n < hi; ++n) {
+      adjacency_of(L, n, a);
+      for (int q = 0; q < 18; ++q) adj[q * ld + n] = a[q];
+    }
+  });
+  for (int q = 0; q < 18; ++q) std::fill(adj + q * ld + L->N, adj + (q + 1) * ld, -1);
   return LBM_OK;
 }
 
