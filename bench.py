@@ -139,6 +139,25 @@ def kernel_key(name):
     return key
 
 
+#: --odd-schedule choices as the solver's odd_schedule argument
+SCHEDULES = {"auto": "auto", "band": "band", "chunked": None}
+#: the --odd-schedule choice of this run (set by main)
+ODD_SCHEDULE = ["auto"]
+
+
+def odd_schedule_name(lat, precision, index_bytes):
+    """The AA odd step's workgroup order of the default line's solver."""
+    from paper_1410_0412_amd import choose_odd_schedule
+    from paper_1410_0412_amd.solver import BAND_ROWS
+
+    if ODD_SCHEDULE[0] == "chunked":
+        return "chunked"
+    if ODD_SCHEDULE[0] == "band":
+        return "band/%d" % BAND_ROWS
+    rows = choose_odd_schedule(lat, "aa", precision, index_bytes)
+    return "band/%d" % rows if rows else "chunked"
+
+
 def slot_bits(n_fluid):
     """Width of the time-step kernels' slot offsets for a lattice of n_fluid
     nodes: 32 while a grid (19 * ldf elements) fits in 2^31 - 1, else 64."""
@@ -348,7 +367,7 @@ def time_variant(torch, lat, p, pattern, ria, precision, steps, warmup, xcd_rema
     from paper_1410_0412_amd import Solver
 
     s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=precision, xcd_remap=xcd_remap,
-               trt_magic=trt_magic)
+               trt_magic=trt_magic, odd_schedule=SCHEDULES[ODD_SCHEDULE[0]] if pattern == "aa" else None)
     index = s.index
     s.init()
     s.step(2 * warmup)
@@ -541,7 +560,8 @@ def size_sweep(torch, args):
         N = lat.n_fluid
         row = {"fluid_nodes": N}
         for prec in ("f64", "f32"):
-            s = Solver(lat, p["tau"], p["force"], pattern="aa", ria="auto", precision=prec)
+            s = Solver(lat, p["tau"], p["force"], pattern="aa", ria="auto", precision=prec,
+                       odd_schedule=SCHEDULES[args.odd_schedule])
             s.init()
             s.step(2 * args.warmup)
             torch.cuda.synchronize()
@@ -552,7 +572,8 @@ def size_sweep(torch, args):
             torch.cuda.synchronize()
             sec = e0.elapsed_time(e1) * 1e-3
             row[prec] = {"index": s.index, "mflups": round(2 * args.steps * N / sec / 1e6, 1),
-                         "us_per_time_step": round(sec / (2 * args.steps) * 1e6, 2)}
+                         "us_per_time_step": round(sec / (2 * args.steps) * 1e6, 2),
+                         "odd_schedule": "band/%d" % s.band_rows if s.band_rows else "chunked"}
             del s
         log(name, row)
         out["workloads"][name] = row
@@ -760,6 +781,9 @@ def main():
                     help="timed AA cycles (2 time steps each) per repeat; the default line takes the median of 5")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--odd-schedule", choices=("auto", "band", "chunked"), default="auto",
+                    help="workgroup order of the AA odd step in the default line and the size sweep "
+                         "(auto: the solver's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD,
@@ -791,6 +815,7 @@ def main():
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32/FP16 deviation storage vs FP64 after --steps time steps on --workload")
     args = ap.parse_args()
+    ODD_SCHEDULE[0] = args.odd_schedule
     if args.order_traffic:
         print(json.dumps(order_traffic(*args.order_traffic), indent=1))
         return
@@ -985,6 +1010,7 @@ def main_line(torch, args):
             "porosity": round(float(1.0 - mask.mean()), 5),
             "tau": p["tau"], "force": list(p["force"]),
             "enumeration": enum,
+            "odd_schedule": odd_schedule_name(lat, "f64", idx_bytes[main_index]),
             "lattice_build_s": round(t_build, 3),
         },
         "roofline": {

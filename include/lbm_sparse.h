@@ -166,6 +166,27 @@ int lbm_lattice_direction_runs(const lbm_lattice* lat, int64_t* n_dir_runs);
 int lbm_lattice_copy_direction_tables(const lbm_lattice* lat, int32_t* dir_delta,
                                       uint64_t* dir_bits, int32_t* dir_base);
 
+/*
+ * Workgroup order for the AA odd step on large lattices (an extension
+ * beyond the paper, for the cache hierarchy of a multi-die GPU). The step
+ * kernels run one workgroup per block of 256 consecutive nodes, and the
+ * device deals workgroup b to die (XCD) b mod 8. In the default order all 8
+ * XCDs sweep the node list together, so a block and its x-neighbours one
+ * x-plane away meet one plane's sweep apart, mostly on different XCDs; once a
+ * plane's traffic outgrows the caches, the lines they share are fetched and
+ * written back twice. The band schedule sweeps y-bands of band_rows rows one
+ * after the other, and inside a band x-plane after x-plane; XCD k takes the
+ * blocks whose first node lies in rows [k, k + 1) * band_rows / 8 of the
+ * band, so a block's x-neighbours follow on the same XCD soon after.
+ * sched: host int32[*len] or NULL. With NULL, *len receives the length the
+ * schedule needs (a multiple of 8). Otherwise *len must be at least that
+ * length; on return sched[8 j + k] is the j-th block of XCD k, or -1 (no
+ * work), and *len the length written. Only for LS order without blocking
+ * (x slowest, z fastest). Errors: LBM_EINVAL (null lattice or len, another
+ * order, band_rows not a positive multiple of 8, *len too small).
+ */
+int lbm_lattice_band_schedule(const lbm_lattice* lat, int32_t band_rows, int32_t* sched, int64_t* len);
+
 void lbm_lattice_free(lbm_lattice* lat);
 
 /* ====================================================================== */
@@ -258,6 +279,23 @@ int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace
 
 /* Set the stream later work is queued on. */
 int lbm_solver_set_stream(lbm_solver* s, void* hip_stream);
+
+/*
+ * Launch the AA odd step's workgroups in the order sched (host int32[len],
+ * len a positive multiple of 8: entry b names the 256-node block that
+ * workgroup b processes, -1 an empty slot; every block of the lattice must
+ * appear exactly once), as lbm_lattice_band_schedule makes it. The library
+ * checks the schedule on the host, copies it into sched_device (a
+ * caller-owned device int32[len] that must outlive the solver's use of it;
+ * the call synchronises the stream) and launches the odd step with len
+ * workgroups from then on. sched = NULL restores the default order. The
+ * even step, OS-NT and the partial-bounce-back and adjoint steps keep the
+ * default order. A step's result does not depend on the order.
+ * Errors: LBM_EINVAL (null solver or sched_device, a bad len, an entry
+ * outside [-1, number of blocks), a block missing or twice), LBM_ESTATE
+ * (OS-NT pattern), LBM_EDEVICE (the copy failed).
+ */
+int lbm_solver_set_odd_schedule(lbm_solver* s, const int32_t* sched, int64_t len, int32_t* sched_device);
 
 /*
  * f(0) = feq(rho, u) on every node and t = 0 (one kernel).

@@ -10,5 +10,5 @@ arguments.
 
 from ._capi import LbmError, lib  # noqa: F401
 from .lattice import Lattice  # noqa: F401
-from .solver import Solver, bench_stream, choose_index, required_bytes  # noqa: F401
+from .solver import Solver, bench_stream, choose_index, choose_odd_schedule, required_bytes  # noqa: F401
 from .adjoint import OutletFlux, outlet_flux  # noqa: F401

@@ -88,12 +88,14 @@ def lib():
         "lbm_lattice_copy_wave_tables": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
         "lbm_lattice_direction_runs": (ctypes.c_int, [vp, c_i64p]),
         "lbm_lattice_copy_direction_tables": (ctypes.c_int, [vp, vp, vp, vp]),
+        "lbm_lattice_band_schedule": (ctypes.c_int, [vp, ctypes.c_int32, vp, c_i64p]),
         "lbm_lattice_free": (None, [vp]),
         "lbm_solver_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), c_i64p]),
         "lbm_required_bytes": (ctypes.c_int, [ctypes.POINTER(Params), c_i64p, c_i64p]),
         "lbm_solver_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(Buffers), vp,
                                              ctypes.c_int64, vp, ctypes.POINTER(vp)]),
         "lbm_solver_set_stream": (ctypes.c_int, [vp, vp]),
+        "lbm_solver_set_odd_schedule": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp]),
         "lbm_solver_init_equilibrium": (ctypes.c_int, [vp, vp, vp]),
         "lbm_solver_step": (ctypes.c_int, [vp, ctypes.c_int64]),
         "lbm_solver_time": (ctypes.c_int, [vp, c_i64p]),
@@ -121,7 +123,7 @@ def lib():
 EXPORTED = [
     "lbm_last_error", "lbm_lattice_build", "lbm_lattice_sizes", "lbm_lattice_copy_nodes",
     "lbm_lattice_copy_adjacency", "lbm_lattice_copy_runs", "lbm_lattice_copy_wave_tables",
-    "lbm_lattice_direction_runs", "lbm_lattice_copy_direction_tables", "lbm_lattice_free", "lbm_solver_workspace_bytes", "lbm_required_bytes", "lbm_solver_create", "lbm_solver_set_stream",
+    "lbm_lattice_direction_runs", "lbm_lattice_copy_direction_tables", "lbm_lattice_band_schedule", "lbm_lattice_free", "lbm_solver_workspace_bytes", "lbm_required_bytes", "lbm_solver_create", "lbm_solver_set_stream", "lbm_solver_set_odd_schedule",
     "lbm_solver_init_equilibrium", "lbm_solver_step", "lbm_solver_time", "lbm_solver_moments", "lbm_solver_moments_static",
     "lbm_solver_export_pdfs", "lbm_solver_import_pdfs", "lbm_solver_free", "lbm_bench_stream",
     "lbm_solver_set_time", "lbm_solver_weighted_momentum", "lbm_adjoint_seed_momentum", "lbm_adjoint_step",

@@ -12,6 +12,11 @@ namespace lbm {
 
 // Nodes per GPU wavefront tile; the RIA wave tables are built for this width.
 constexpr int64_t kWave = 64;
+// Nodes per workgroup of the step kernels (four wavefront tiles), the unit
+// of a workgroup schedule.
+constexpr int64_t kGroupNodes = 256;
+// XCDs of the device: the hardware deals workgroup b to XCD b mod 8.
+constexpr int64_t kXcds = 8;
 
 inline char* error_buffer() {
   static thread_local char buf[512] = {0};

@@ -36,6 +36,7 @@
 namespace lbm {
 
 constexpr int kBlock = 256;
+static_assert(kBlock == kGroupNodes, "a workgroup covers one schedule block");
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, so in
 // plain order neighbouring tiles run on different XCDs and the cache lines
@@ -50,6 +51,12 @@ __device__ __forceinline__ int64_t tile_index(int chunk) {
   if (chunk <= 0) return blockIdx.x;
   const int64_t k = chunk, x = blockIdx.x & 7, seq = blockIdx.x >> 3;
   return ((seq / k) * 8 + x) * k + seq % k;
+}
+
+// A workgroup's tile from an explicit schedule (host-validated: every tile
+// once, -1 for an empty slot), or from the chunked order without one.
+__device__ __forceinline__ int64_t scheduled_tile(int chunk, const int32_t* __restrict__ sched) {
+  return sched ? (int64_t)sched[blockIdx.x] : tile_index(chunk);
 }
 
 // ---------------------------------------------------------------- indices --
@@ -193,8 +200,10 @@ template <class S> struct OddWaves { static constexpr int value = sizeof(S) == 2
 
 template <class S, class Idx, bool TRT, class Off>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OddWaves<S>::value)))
-aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int chunk) {
-  const int64_t n64 = tile_index(chunk) * kBlock + threadIdx.x;
+aa_odd(S* __restrict__ F, int32_t N, Idx idx, Collision c, int chunk, const int32_t* __restrict__ sched) {
+  const int64_t tile = scheduled_tile(chunk, sched);
+  if (tile < 0) return;
+  const int64_t n64 = tile * kBlock + threadIdx.x;
   if (n64 >= N) return;
   const int32_t n = (int32_t)n64;
   int32_t a[18];

@@ -31,6 +31,7 @@ using namespace lbm;
 struct lbm_lattice {
   int32_t nx = 0, ny = 0, nz = 0;
   uint32_t periodic = 0;            // bit a: axis a periodic
+  bool plain_lex = false;           // LS order without blocking
   int64_t N = 0, R = 0, W = 0;
   std::vector<int32_t> node_voxel;  // [N]
   std::vector<int32_t> node_of;     // [nx*ny*nz]: node of a voxel, -1 if solid
@@ -380,6 +381,7 @@ int lbm_lattice_build(const uint8_t* solid, int32_t nx, int32_t ny, int32_t nz,
     }
     L->N = (int64_t)L->node_voxel.size();
     L->periodic = periodic_mask;
+    L->plain_lex = order == LBM_ORDER_LEX && (block <= 1 || block >= std::max(nx, std::max(ny, nz)));
     build_node_map(L);
     build_runs(L);
   } catch (const std::bad_alloc&) {
@@ -463,6 +465,52 @@ int lbm_lattice_copy_direction_tables(const lbm_lattice* L, int32_t* dir_delta, 
   if (dir_delta && L->RD) std::memcpy(dir_delta, L->dir_delta.data(), sizeof(int32_t) * L->RD);
   if (dir_bits && L->W) std::memcpy(dir_bits, L->dir_bits.data(), sizeof(uint64_t) * 18 * L->W);
   if (dir_base && L->W) std::memcpy(dir_base, L->dir_base.data(), sizeof(int32_t) * 18 * L->W);
+  return LBM_OK;
+}
+
+int lbm_lattice_band_schedule(const lbm_lattice* L, int32_t band_rows, int32_t* sched, int64_t* len) {
+  clear_error();
+  if (!L || !len) return fail(LBM_EINVAL, "null pointer");
+  if (!L->plain_lex) return fail(LBM_EINVAL, "band schedules need LS order without blocking");
+  if (band_rows <= 0 || band_rows % kXcds != 0)
+    return fail(LBM_EINVAL, "band_rows must be a positive multiple of %d", (int)kXcds);
+  const int64_t G = (L->N + kGroupNodes - 1) / kGroupNodes;
+  const int64_t ny = L->ny, nz = L->nz;
+  // a block belongs to the band, x-plane and XCD of its first node: XCD k
+  // takes rows [k, k + 1) * band_rows / 8 of every band
+  std::vector<int64_t> count((size_t)kXcds, 0);
+  for (int64_t g = 0; g < G; ++g) {
+    const int64_t v = L->node_voxel[g * kGroupNodes];
+    const int64_t y = (v / nz) % ny;
+    ++count[(size_t)(((y % band_rows) * kXcds) / band_rows)];
+  }
+  const int64_t per = *std::max_element(count.begin(), count.end());
+  const int64_t need = per * kXcds;
+  if (!sched) {
+    *len = need;
+    return LBM_OK;
+  }
+  if (*len < need) return fail(LBM_EINVAL, "the schedule needs %lld entries", (long long)need);
+  // blocks in (band, x-plane, node) order, dealt to their XCD's list
+  const int64_t nxp = L->nx;
+  std::vector<int64_t> key((size_t)G);
+  std::vector<int64_t> order((size_t)G);
+  for (int64_t g = 0; g < G; ++g) {
+    const int64_t v = L->node_voxel[g * kGroupNodes];
+    const int64_t x = v / (ny * nz), y = (v / nz) % ny;
+    key[(size_t)g] = (y / band_rows) * nxp + x;
+    order[(size_t)g] = g;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return key[(size_t)a] < key[(size_t)b]; });
+  std::vector<int64_t> next((size_t)kXcds, 0);
+  std::fill(sched, sched + need, -1);
+  for (int64_t i = 0; i < G; ++i) {
+    const int64_t g = order[(size_t)i];
+    const int64_t v = L->node_voxel[g * kGroupNodes];
+    const int64_t k = (((v / nz) % ny % band_rows) * kXcds) / band_rows;
+    sched[next[(size_t)k]++ * kXcds + k] = (int32_t)g;
+  }
+  *len = need;
   return LBM_OK;
 }
 

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <new>
 #include <type_traits>
+#include <vector>
 
 #include "common.hpp"
 #include "adjoint.hpp"
@@ -31,6 +32,8 @@ struct lbm_solver {
   unsigned even_lds = 0, pull_lds = 0;  // LDS bytes reserved per workgroup
   bool trt = false;
   Collision c;
+  const int32_t* odd_sched = nullptr;  // device schedule of the AA odd step, or null
+  int64_t odd_sched_len = 0;
 };
 
 namespace {
@@ -413,10 +416,11 @@ void launch_step_op(lbm_solver* s, int32_t N) {
       // the scattered stores of the odd step share partial lines between
       // neighbouring tiles: keep neighbours on one XCD
       const int chunk = s->remap ? kOddChunk : 0;
+      const unsigned grid = s->odd_sched ? (unsigned)s->odd_sched_len : chunked_grid(tiles, chunk);
       dispatch(s, s->b.pdf[0], [&](auto* F, auto idx) {
         using S = std::remove_pointer_t<decltype(F)>;
-        hipLaunchKernelGGL((aa_odd<S, decltype(idx), TRT, Off>), dim3(chunked_grid(tiles, chunk)), b, 0,
-                           s->stream, F, N, idx, s->c, chunk);
+        hipLaunchKernelGGL((aa_odd<S, decltype(idx), TRT, Off>), dim3(grid), b, 0, s->stream, F, N, idx, s->c,
+                           chunk, s->odd_sched);
       });
     }
   } else {
@@ -585,6 +589,40 @@ int lbm_solver_create(const lbm_params* p, const lbm_buffers* b, void* workspace
     c.h_unscale[q] = 1.0f / c.h_scale[q];
   }
   *out = s;
+  return LBM_OK;
+}
+
+int lbm_solver_set_odd_schedule(lbm_solver* s, const int32_t* sched, int64_t len, int32_t* sched_device) {
+  clear_error();
+  if (!s) return fail(LBM_EINVAL, "null solver");
+  if (!sched) {
+    s->odd_sched = nullptr;
+    s->odd_sched_len = 0;
+    return LBM_OK;
+  }
+  if (s->p.pattern != LBM_PATTERN_AA) return fail(LBM_ESTATE, "only the AA pattern's odd step takes a schedule");
+  if (!sched_device) return fail(LBM_EINVAL, "sched_device is null");
+  if (len <= 0 || len % kXcds != 0 || len > (int64_t)INT32_MAX)
+    return fail(LBM_EINVAL, "len must be a positive multiple of %d below 2^31", (int)kXcds);
+  const int64_t G = (s->p.n_fluid + kGroupNodes - 1) / kGroupNodes;
+  std::vector<uint8_t> seen((size_t)G, 0);
+  int64_t blocks = 0;
+  for (int64_t i = 0; i < len; ++i) {
+    const int64_t g = sched[i];
+    if (g == -1) continue;
+    if (g < 0 || g >= G) return fail(LBM_EINVAL, "schedule entry %lld is %lld, outside [-1, %lld)", (long long)i,
+                                     (long long)g, (long long)G);
+    if (seen[(size_t)g]) return fail(LBM_EINVAL, "block %lld appears twice in the schedule", (long long)g);
+    seen[(size_t)g] = 1;
+    ++blocks;
+  }
+  if (blocks != G) return fail(LBM_EINVAL, "the schedule covers %lld of %lld blocks", (long long)blocks, (long long)G);
+  if (hipMemcpyAsync(sched_device, sched, (size_t)len * sizeof(int32_t), hipMemcpyHostToDevice, s->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return device_status("set_odd_schedule (copy)");
+  s->odd_sched = sched_device;
+  s->odd_sched_len = len;
   return LBM_OK;
 }
 

@@ -93,6 +93,22 @@ class Lattice:
             self._rd = rd.value
         return self._rd
 
+    @property
+    def plain_lex(self):
+        """LS order without blocking (x slowest, z fastest)."""
+        return self.order == "lex" and (self.block <= 1 or self.block >= max(self.shape))
+
+    def band_schedule(self, band_rows=32):
+        """Workgroup order of the AA odd step that sweeps y-bands of
+        ``band_rows`` rows plane by plane, XCD k taking rows k/8 of every
+        band (lbm_lattice_band_schedule); int32, -1 for empty slots."""
+        L = _capi.lib()
+        n = ctypes.c_int64()
+        _capi.check(L.lbm_lattice_band_schedule(self._h, int(band_rows), None, ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.int32)
+        _capi.check(L.lbm_lattice_band_schedule(self._h, int(band_rows), _ptr(out), ctypes.byref(n)))
+        return out[: n.value]
+
     def direction_tables(self):
         """(dir_delta int32 (RD,), dir_bits uint64 (W, 18), dir_base int32 (W, 18))."""
         delta = np.empty(self.n_direction_runs, dtype=np.int32)

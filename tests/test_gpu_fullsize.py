@@ -353,10 +353,30 @@ def foam512():
 W_Q = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 
 
+def test_foam384_band_schedule_bitwise(foam):
+    # the default line's lattice with the odd step in the band order (32
+    # rows), 20 steps: bitwise the default order's state
+    from paper_1410_0412_amd import Lattice, Solver
+    mask, p = foam
+    lat = Lattice(mask, p["periodic"], p["order"], p["block"])
+    out = []
+    for sched in (None, "band"):
+        print("case foam-384 odd schedule", sched, flush=True)
+        s = Solver(lat, p["tau"], p["force"], pattern="aa", ria="direction", odd_schedule=sched)
+        s.init()
+        s.step(20)
+        out.append(s.export_pdfs())
+        del s
+    assert torch.equal(out[0], out[1])
+    del out
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("pattern,ria,prec,pbb", [
     ("aa", "auto", "f64", False), ("osnt", "auto", "f64", False), ("aa", False, "f64", False),
     ("aa", True, "f64", False), ("osnt", True, "f64", False), ("aa", "auto", "f64", True),
-    ("aa", "auto", "f32", False), ("osnt", "auto", "f32", False), ("aa", "auto", "f16", False)])
+    ("aa", "auto", "f32", False), ("osnt", "auto", "f32", False), ("aa", "auto", "f16", False),
+    ("aa", "band", "f64", False)])
 def test_foam512_wide_slots_sampled_sites(foam512, pattern, ria, prec, pbb):
     # sampled sites after 3 steps against the oracle's dependency cone:
     # bitwise in FP64 (with partial bounce-back at ns = 0 too), within the
@@ -364,7 +384,9 @@ def test_foam512_wide_slots_sampled_sites(foam512, pattern, ria, prec, pbb):
     # a value from a wrong slot is off by about 3 |c_q . du| ~ 4e-2)
     from paper_1410_0412_amd import Solver
     lat, p, steps, r, v, node, want = foam512
-    s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria=ria, precision=prec, pbb=pbb)
+    band = ria == "band"  # per-direction runs with the odd step in the band order
+    s = Solver(lat, p["tau"], p["force"], pattern=pattern, ria="auto" if band else ria, precision=prec, pbb=pbb,
+               odd_schedule="band" if band else "auto")
     print("case 64-bit slots:", pattern, "index", s.index, prec, "pbb" if pbb else "", flush=True)
     s.init(torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda())
     s.step(steps)

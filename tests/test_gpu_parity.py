@@ -94,6 +94,49 @@ def test_wide_slots_every_step(pattern, ria, prec, trt):
             assert np.array_equal(fa.cpu().numpy(), oracle_at_nodes(lat, f)), t
 
 
+@pytest.mark.parametrize("ria", [False, True, "direction"])
+@pytest.mark.parametrize("prec,trt,rows", [("f64", None, 8), ("f64", None, 16), ("f64", 0.1875, 8),
+                                           ("f32", None, 8), ("f16", None, 16)])
+def test_band_schedule_every_step(ria, prec, trt, rows):
+    # the AA odd step launched in the band schedule's order gives the default
+    # order's result bit for bit after every step; FP64 equals the oracle
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.25, PER, seed=5)
+    rho0, u0 = init_fields(mask.shape, seed=6)
+    tau, F = 0.65, (2e-5, -1e-5, 5e-6)
+    print("case band schedule", ria, prec, trt, rows, flush=True)
+    lat, a = solver_for(mask, PER, tau, F, "aa", ria, precision=prec, trt_magic=trt, odd_schedule="band",
+                        band_rows=rows)
+    _, b = solver_for(mask, PER, tau, F, "aa", ria, precision=prec, trt_magic=trt, odd_schedule=None)
+    assert a.band_rows == rows and b.odd_sched is None
+    r, v = node_fields(lat, rho0, u0)
+    r, v = torch.from_numpy(r).cuda(), torch.from_numpy(v).cuda()
+    a.init(r, v)
+    b.init(r, v)
+    f = dense.initial_state(mask.astype(bool), rho0, u0)
+    for t in range(1, 8):
+        a.step(1)
+        b.step(1)
+        fa = a.export_pdfs()
+        assert torch.equal(fa, b.export_pdfs()), t
+        if prec == "f64":
+            f = dense.step(f, mask.astype(bool), PER, tau, F, trt)
+            assert np.array_equal(fa.cpu().numpy(), oracle_at_nodes(lat, f)), t
+
+
+def test_band_schedule_reset_and_auto():
+    # NULL restores the default order; "auto" keeps it on small planes
+    from paper_1410_0412_amd import _capi
+    mask = rsa_spheres((20, 18, 22), 2.5, 0.25, PER, seed=5)
+    lat, s = solver_for(mask, PER, 0.7, (1e-5, 0, 0), "aa", "direction", odd_schedule="band", band_rows=8)
+    _, ref = solver_for(mask, PER, 0.7, (1e-5, 0, 0), "aa", "direction")
+    assert ref.odd_sched is None and ref.band_rows is None
+    s.init(); ref.init()
+    s.step(3); ref.step(3)
+    _capi.check(_capi.lib().lbm_solver_set_odd_schedule(s._h, None, 0, None))
+    s.step(4); ref.step(4)
+    assert torch.equal(s.export_pdfs(), ref.export_pdfs())
+
+
 @pytest.mark.parametrize("pattern,ria", VARIANTS)
 def test_import_export_roundtrip(pattern, ria):
     mask = rsa_spheres((16, 16, 16), 2.0, 0.2, PER, seed=7)
