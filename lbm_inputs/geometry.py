@@ -240,6 +240,10 @@ WORKLOADS = {
     "foam-512": dict(
         shape=(512, 512, 512), periodic=(True, False, False), tau=0.7,
         force=(1e-6, 0.0, 0.0), order="lex", block=0, steps=500),
+    # the same foam at 768^3 (385 M fluid nodes, a 59 GB FP64 grid)
+    "foam-768": dict(
+        shape=(768, 768, 768), periodic=(True, False, False), tau=0.7,
+        force=(1e-6, 0.0, 0.0), order="lex", block=0, steps=500),
     # the same foam at 1024^3 (about 913 M fluid nodes, a 139 GB FP64 grid):
     # one GPU's memory nearly full
     "foam-1024": dict(
@@ -264,7 +268,7 @@ def workload(name: str, seed: int = 0):
         mask = relaxed_spheres(shape, 8.0, 0.40, seed)
     elif name == "spherepack-128":
         mask = relaxed_spheres(shape, 8.0, 0.50, seed)
-    elif name in ("foam-384", "foam-512", "foam-1024"):
+    elif name in ("foam-384", "foam-512", "foam-768", "foam-1024"):
         mask = foam(shape, 4.0, 0.85, seed)
     else:
         raise KeyError(name)
