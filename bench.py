@@ -782,7 +782,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--odd-schedule", choices=("auto", "band", "chunked"), default="auto",
-                    help="workgroup order of the AA odd step in the default line and the size sweep "
+                    help="workgroup order of the AA odd step in every AA line of the run "
                          "(auto: the solver's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
