@@ -48,6 +48,25 @@ def test_header_symbols_exported():
         assert hasattr(lib, name), name
 
 
+def test_header_is_c99_and_links(tmp_path):
+    # the header is plain C: a C99 program that takes the address of every
+    # declared entry point compiles with -pedantic and links against the
+    # library (no device is touched: nothing is called)
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    body = "\n".join("    (void)&%s;" % name for name in sorted(_capi.EXPORTED))
+    src.write_text('#include "lbm_sparse.h"\nint main(void) {\n%s\n    return 0;\n}\n' % body)
+    lib_dir = os.path.dirname(_capi.LIB_PATH)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), str(src), "-L", lib_dir, "-llbm_sparse",
+                        "-Wl,-rpath," + lib_dir, "-o", str(tmp_path / "abi")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 @pytest.mark.parametrize("order,block", [("lex", 0), ("lex", 1), ("lex", 2), ("lex", 3), ("lex", 5), ("morton", 0),
                                          ("hilbert", 0), ("hilbert_ls", 1), ("hilbert_ls", 3)])
 def test_tiny_masks_all_periodicities(order, block):
