@@ -6,7 +6,7 @@
 // runtime is used, so the program shows the library driven without Python.
 //
 // usage: lbm_run MASK NX NY NZ PERIODIC ORDER BLOCK PATTERN INDEX PRECISION
-//                TAU FX FY FZ STEPS OUT
+//                TAU FX FY FZ STEPS OUT [BAND_ROWS]
 //   MASK       file of NX*NY*NZ bytes in C order (x slowest); nonzero = solid
 //   PERIODIC   bit mask of the periodic axes (1 = x, 2 = y, 4 = z)
 //   ORDER      lex | morton | hilbert | hilbert_ls (BLOCK: blocking factor,
@@ -14,6 +14,9 @@
 //   PATTERN    aa | osnt
 //   INDEX      adjacency | runs | direction
 //   PRECISION  f64 | f32 | f16
+//   BAND_ROWS  optional: launch the AA odd step in the band schedule with
+//              this many rows per band (lbm_lattice_band_schedule); 0 or
+//              absent: the default order
 // OUT receives int64 N, int32 node_voxel[N] and double f[19][N] (f(STEPS),
 // direction-major). One line on stdout reports N, the runs and the totals
 // (mass, jx, jy, jz). Exit status 0 on success, 1 on any error.
@@ -69,12 +72,14 @@ int pick(const char* s, const char* const* names, int count, const char* what) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 17) {
+  if (argc != 17 && argc != 18) {
     std::fprintf(stderr,
-                 "usage: %s MASK NX NY NZ PERIODIC ORDER BLOCK PATTERN INDEX PRECISION TAU FX FY FZ STEPS OUT\n",
+                 "usage: %s MASK NX NY NZ PERIODIC ORDER BLOCK PATTERN INDEX PRECISION TAU FX FY FZ STEPS OUT"
+                 " [BAND_ROWS]\n",
                  argv[0]);
     return 1;
   }
+  const int32_t band_rows = argc == 18 ? std::atoi(argv[17]) : 0;
   const int32_t nx = std::atoi(argv[2]), ny = std::atoi(argv[3]), nz = std::atoi(argv[4]);
   const uint32_t periodic = (uint32_t)std::atoi(argv[5]);
   static const char* const kOrders[] = {"lex", "morton", "hilbert", "hilbert_ls"};
@@ -128,7 +133,7 @@ int main(int argc, char** argv) {
   // grid and workspace sizes as the library states them
   int64_t grid_bytes = 0, ws_bytes = 0;
   check(lbm_required_bytes(&p, &grid_bytes, &ws_bytes), "required bytes");
-  DeviceBuffer grid[2], adj, delta, bits, base, ws, f_dev, tot_dev;
+  DeviceBuffer grid[2], adj, delta, bits, base, ws, f_dev, tot_dev, sched_dev;
   grid[0].alloc((size_t)grid_bytes, "grid allocation");
   if (pattern == LBM_PATTERN_OSNT) grid[1].alloc(grid_bytes, "grid allocation");
 
@@ -160,6 +165,14 @@ int main(int argc, char** argv) {
     bits.upload(b1, "run table upload");
     base.upload(b0, "run table upload");
   }
+  // the odd step's band schedule, built from the lattice before it is freed
+  std::vector<int32_t> sched;
+  if (band_rows > 0) {
+    int64_t len = 0;
+    check(lbm_lattice_band_schedule(lat, band_rows, nullptr, &len), "band schedule");
+    sched.resize((size_t)len);
+    check(lbm_lattice_band_schedule(lat, band_rows, sched.data(), &len), "band schedule");
+  }
   lbm_lattice_free(lat);
 
   lbm_buffers b;
@@ -176,6 +189,10 @@ int main(int argc, char** argv) {
   check_hip(hipStreamCreate(&stream), "stream");
   lbm_solver* s = nullptr;
   check(lbm_solver_create(&p, &b, ws.p, ws_bytes, stream, &s), "solver create");
+  if (!sched.empty()) {
+    sched_dev.alloc(sched.size() * sizeof(int32_t), "schedule allocation");
+    check(lbm_solver_set_odd_schedule(s, sched.data(), (int64_t)sched.size(), (int32_t*)sched_dev.p), "odd schedule");
+  }
   check(lbm_solver_init_equilibrium(s, nullptr, nullptr), "init");
   check(lbm_solver_step(s, steps), "step");
 

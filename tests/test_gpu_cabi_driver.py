@@ -20,7 +20,7 @@ PER = (True, False, False)
 TAU, FORCE = 0.8, (1e-5, 2e-6, 0.0)
 
 
-def run_driver(tmp_path, mask, order, block, pattern, index, prec, steps, mask_bytes=None):
+def run_driver(tmp_path, mask, order, block, pattern, index, prec, steps, mask_bytes=None, band_rows=None):
     if not os.path.exists(DRIVER):
         pytest.fail("lbm_run is not built (run the package's build.py)")
     mpath = tmp_path / "mask.u8"
@@ -29,8 +29,8 @@ def run_driver(tmp_path, mask, order, block, pattern, index, prec, steps, mask_b
     bits = sum(1 << a for a in range(3) if PER[a])
     cmd = [DRIVER, str(mpath)] + [str(n) for n in mask.shape] + [str(bits), order, str(block), pattern, index, prec,
                                                                   repr(TAU)] + [repr(v) for v in FORCE] + [
-        str(steps), str(out)]
-    print("case lbm_run", order, block, pattern, index, prec, steps, flush=True)
+        str(steps), str(out)] + ([str(band_rows)] if band_rows is not None else [])
+    print("case lbm_run", order, block, pattern, index, prec, steps, band_rows, flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
     return r, out
 
@@ -64,6 +64,21 @@ def test_driver_fp64_bitwise(tmp_path, case, pattern, index):
     mass = float(r.stdout.split("mass=")[1].split()[0])
     want = f.sum()
     assert abs(mass - want) <= 1e-13 * want
+
+
+@pytest.mark.parametrize("index", ["runs", "direction"])
+def test_driver_band_schedule(tmp_path, case, index):
+    # the odd step in the band schedule, set up through the C ABI alone:
+    # bitwise the oracle in FP64; OS-NT takes no schedule
+    mask, steps, ref = case
+    r, out = run_driver(tmp_path, mask, "lex", 0, "aa", index, "f64", steps, band_rows=8)
+    assert r.returncode == 0, r.stderr
+    nv, f = read_output(out)
+    assert np.array_equal(f, ref[:, nv])
+    r, _ = run_driver(tmp_path, mask, "lex", 0, "osnt", index, "f64", steps, band_rows=8)
+    assert r.returncode == 1 and "odd schedule" in r.stderr
+    r, _ = run_driver(tmp_path, mask, "lex", 4, "aa", index, "f64", steps, band_rows=8)
+    assert r.returncode == 1 and "band schedule" in r.stderr
 
 
 def test_driver_morton_and_fp32(tmp_path, case):
