@@ -139,8 +139,10 @@ class Solver:
                result bit for bit.
     odd_schedule  workgroup order of the AA odd step: "auto" (default):
                :func:`choose_odd_schedule`; "band": the band schedule with
-               ``band_rows`` rows; None: the default chunked order. The
-               result is the same bit for bit.
+               ``band_rows`` rows (AA pattern and LS order without
+               blocking only; nothing to order on an empty lattice);
+               None: the default chunked order. The result is the same
+               bit for bit.
     """
 
     def __init__(self, lattice, tau, force=(0.0, 0.0, 0.0), pattern="aa", ria="auto",
@@ -225,7 +227,8 @@ class Solver:
                 ib = lattice.index_bytes()[self.index] if self.index != "adjacency" else 72.0
                 rows = choose_odd_schedule(lattice, pattern, precision, ib)
             elif odd_schedule == "band":
-                rows = int(band_rows)
+                # an empty lattice has no odd-step blocks to order
+                rows = int(band_rows) if lattice.n_fluid else None
             elif odd_schedule is None:
                 rows = None
             else:

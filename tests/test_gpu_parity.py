@@ -177,11 +177,14 @@ def test_small_and_ragged(shape, periodic, pattern, ria):
 def test_empty_lattice(pattern, ria):
     from paper_1410_0412_amd import Lattice, Solver
     lat = Lattice(np.ones((4, 4, 4), np.uint8))
-    s = Solver(lat, 0.8, (1e-6, 0, 0), pattern=pattern, ria=ria)
-    s.init()
-    s.step(3)
-    rho, u, tot = s.moments()
-    assert rho.numel() == 0 and s.t == 3 and float(tot.abs().sum()) == 0.0
+    sched = ("auto", "band") if pattern == "aa" else ("auto",)
+    for odd_schedule in sched:
+        s = Solver(lat, 0.8, (1e-6, 0, 0), pattern=pattern, ria=ria, odd_schedule=odd_schedule)
+        assert s.odd_sched is None
+        s.init()
+        s.step(3)
+        rho, u, tot = s.moments()
+        assert rho.numel() == 0 and s.t == 3 and float(tot.abs().sum()) == 0.0
 
 
 def test_rest_state_and_no_remap():
