@@ -47,6 +47,11 @@ class Lattice:
         _capi.check(L.lbm_lattice_sizes(h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(w)))
         self.n_fluid, self.n_runs, self.n_waves = n.value, r.value, w.value
 
+    @classmethod
+    def from_mask(cls, mask, periodic=(True, False, False), order="lex", block=0):
+        """The lattice of ``mask``; the same as the constructor."""
+        return cls(mask, periodic, order, block)
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:

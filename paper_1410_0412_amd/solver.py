@@ -294,6 +294,14 @@ class Solver:
         self._call(_capi.lib().lbm_solver_moments, _vp(rho), _vp(u), _vp(tot))
         return rho, u, tot
 
+    def totals(self):
+        """(4,) float64 on the device: mass, jx, jy, jz of f(t), summed in
+        the fixed order of :meth:`moments` (the same values bit for bit),
+        without writing the per-node fields."""
+        tot = self.torch.empty(4, dtype=self.torch.float64, device=self.device)
+        self._call(_capi.lib().lbm_solver_moments, None, None, _vp(tot))
+        return tot
+
     def moments_static(self):
         """As :meth:`moments`, through ``lbm_solver_moments_static``: the
         reduction's partial sums go to the library's static device scratch

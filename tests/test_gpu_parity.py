@@ -249,6 +249,8 @@ def test_totals_are_reproducible():
         s.step(3)
         tots = [s.moments()[2].cpu().numpy() for _ in range(3)]
         assert all(np.array_equal(t, tots[0]) for t in tots), (pattern, ria)
+        # the totals alone, without the per-node fields
+        assert np.array_equal(s.totals().cpu().numpy(), tots[0]), (pattern, ria)
         if seen is None:
             seen = tots[0]
         assert np.array_equal(tots[0], seen), (pattern, ria)

@@ -118,6 +118,15 @@ def test_empty_and_full():
     assert L.n_fluid == 60
 
 
+def test_from_mask_is_the_constructor():
+    mask = rsa_spheres((20, 18, 16), 3.0, 0.3, (True, False, False), seed=5)
+    a = Lattice.from_mask(mask, (True, False, False), "lex", 4)
+    b = Lattice(mask, (True, False, False), "lex", 4)
+    assert (a.n_fluid, a.n_runs, a.n_waves) == (b.n_fluid, b.n_runs, b.n_waves)
+    assert np.array_equal(a.node_voxel(), b.node_voxel())
+    assert np.array_equal(a.adjacency(), b.adjacency())
+
+
 def test_errors():
     with pytest.raises(LbmError) as e:
         Lattice(np.zeros((2, 2, 2), np.uint8), order="lex", block=-1)
