@@ -101,10 +101,9 @@ def source_digest(read=None):
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch from committed rocprofv3 counter runs
-    (profiles/traffic.json for the default workload, or
-    profiles/traffic_<workload>.json), if the kernel sources have not changed
-    since the counters were taken."""
-    for name in ("traffic.json", "traffic_%s.json" % workload):
+    (profiles/traffic_<workload>.json), if the kernel sources have not
+    changed since the counters were taken."""
+    for name in ("traffic_%s.json" % workload,):
         try:
             with open(os.path.join(ROOT, "profiles", name)) as fh:
                 doc = json.load(fh)
@@ -193,7 +192,7 @@ def _counter_clusters(path, counters):
 
 
 def traffic_from(fetch_csv, write_csv, workload_name, command, out_path=None, rdreq_csv=None, wrreq_csv=None):
-    """Write profiles/traffic.json (or out_path) from two rocprofv3 --pmc runs
+    """Write profiles/traffic_<workload>.json (or out_path) from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch). Both counters are scaled by
     what they read for the copy micro-benchmark, whose bytes are known.
 
@@ -251,7 +250,7 @@ def traffic_from(fetch_csv, write_csv, workload_name, command, out_path=None, rd
             "note": "bytes per L2-to-memory read request of the copy kernel (its bytes over TCC_EA0_RDREQ_sum); "
                     "FETCH_SIZE counts a request as 64 B unless TCC_BUBBLE marks it as 128 B, and TCC_BUBBLE "
                     "reads 0 here, hence the fetch scale of 2"}
-    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic_%s.json" % workload_name), "w") as fh:
         json.dump(doc, fh, indent=1)
     return doc
 
@@ -290,7 +289,7 @@ def order_traffic(sweep_json, fetch_csv, write_csv, tcp_csv, scale_fetch=2.0, sc
     per-direction runs in FP64 and FP32, so the k-th cluster of a kernel's
     dispatches belongs to the k-th variant that runs it. Memory bytes use the
     FETCH_SIZE and WRITE_SIZE scales of the copy kernel (from
-    profiles/traffic.json); L1-to-L2 request sizes are those that put the
+    profiles/traffic_foam-384.json); L1-to-L2 request sizes are those that put the
     FP64 even step of the first order on its algorithmic bytes."""
     sweep = json.load(open(sweep_json))
     orders = list(sweep["orders"])
@@ -799,9 +798,9 @@ def main():
     ap.add_argument("--traffic-requests", nargs=2, metavar=("RDREQ_CSV", "WRREQ_CSV"),
                     help="with --traffic-from: request-count counter files for the cross-check")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
+                    help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc counter files and exit")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
-    ap.add_argument("--traffic-out", default=None, help="with --traffic-from: write here instead of profiles/traffic.json")
+    ap.add_argument("--traffic-out", default=None, help="with --traffic-from: write here instead of profiles/traffic_<workload>.json")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the forward PBB step, the adjoint step and one gradient on the 128^3 sphere pack")
     ap.add_argument("--micro-sizes", default=None,
